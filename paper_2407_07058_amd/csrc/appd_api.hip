@@ -1,0 +1,82 @@
+// C ABI of libappd (declared in include/appd.h): argument checks, workspace,
+// error reporting.  All compute is enqueued by the kernels' launchers.
+#include "appd.h"
+#include "appd_internal.h"
+
+namespace {
+
+thread_local int g_last = APPD_OK;
+
+int fail(int code) {
+    g_last = code;
+    return code;
+}
+
+int ok() {
+    g_last = APPD_OK;
+    return APPD_OK;
+}
+
+bool bad_n(int n) { return n < 1 || n > APPD_MAX_N; }
+
+}  // namespace
+
+extern "C" {
+
+const char* appd_error_string(int code) {
+    switch (code) {
+        case APPD_OK: return "APPD_OK: success";
+        case APPD_EINVAL: return "APPD_EINVAL: invalid argument (null pointer, n out of range, workspace too small or bad mode)";
+        case APPD_EHIP: return "APPD_EHIP: HIP runtime call or kernel launch failed";
+        case APPD_ENOMEM: return "APPD_ENOMEM: device allocation failed";
+        default: return "unknown appd status code";
+    }
+}
+
+int appd_get_last_error(void) { return g_last; }
+
+size_t appd_forward_workspace_bytes(int n) {
+    if (bad_n(n)) return 0;
+    return appd::single_workspace_bytes(n);
+}
+
+int appd_forward_ex(const float* W, int n, int mode, float* M, int32_t* idx, int32_t* order,
+                    int32_t* parent, void* ws, size_t ws_bytes, void* stream) {
+    if (bad_n(n) || !W || !M || !idx || (mode != APPD_MINIMAX && mode != APPD_WIDEST))
+        return fail(APPD_EINVAL);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t need = appd::single_workspace_bytes(n);
+    void* buf = ws;
+    if (ws) {
+        if (ws_bytes < need || ((uintptr_t)ws & 255u)) return fail(APPD_EINVAL);
+    } else {
+        if (hipMallocAsync(&buf, need, s) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(APPD_ENOMEM);
+        }
+    }
+    appd::SingleWs w = appd::carve_single(buf, n);
+    if (order) w.order = order;
+    if (parent) w.parent = parent;
+    hipError_t e = appd::run_single(W, n, mode, M, idx, w, s);
+    if (!ws) {
+        if (hipFreeAsync(buf, s) != hipSuccess && e == hipSuccess) e = hipErrorUnknown;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(APPD_EHIP);
+    }
+    return ok();
+}
+
+int appd_forward_ws(const float* W, int n, float* M, int32_t* idx, void* ws, size_t ws_bytes,
+                    void* stream) {
+    if (!ws) return fail(APPD_EINVAL);
+    return appd_forward_ex(W, n, APPD_MINIMAX, M, idx, nullptr, nullptr, ws, ws_bytes, stream);
+}
+
+int appd_forward(const float* W, int n, float* M, int32_t* idx, void* stream) {
+    return appd_forward_ex(W, n, APPD_MINIMAX, M, idx, nullptr, nullptr, nullptr, 0, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+// Single-graph APPD: persistent Prim kernel, column-block prep, row fill.
+#include "appd_fill.h"
+#include "appd_internal.h"
+#include "appd_prim.h"
+
+namespace appd {
+
+constexpr int kPrimThreads = 1024;
+constexpr int kFillCB = 1024;
+constexpr int kFillThreads = 256;
+constexpr int kFillRowsPerWG = 32;
+
+template <int CH, bool WIDEST>
+__global__ __launch_bounds__(kPrimThreads) void prim_single_kernel(const float* __restrict__ W,
+                                                                   int n, PrimOut out) {
+    __shared__ uint64_t red_key[2 * (kPrimThreads / kWave)];
+    __shared__ int32_t red_v[2 * (kPrimThreads / kWave)];
+    prim_run<kPrimThreads, CH, WIDEST>(W, n, out, red_key, red_v);
+}
+
+template <int CB>
+__global__ __launch_bounds__(kFillThreads) void fill_prep_kernel(const int32_t* __restrict__ pos,
+                                                                 const uint64_t* __restrict__ ek,
+                                                                 int n, uint16_t* blk_sp,
+                                                                 uint16_t* blk_slot,
+                                                                 uint64_t* blk_gap) {
+    __shared__ uint32_t keys[CB];
+    fill_prep_block<CB>(pos, ek, n, blockIdx.x, blk_sp, blk_slot, blk_gap, keys);
+}
+
+template <int CB, bool WIDEST>
+__global__ __launch_bounds__(kFillThreads) void fill_kernel(
+    const int32_t* __restrict__ pos, const uint64_t* __restrict__ ek, int n,
+    const uint16_t* __restrict__ blk_sp, const uint16_t* __restrict__ blk_slot,
+    const uint64_t* __restrict__ blk_gap, float* __restrict__ M, int32_t* __restrict__ idx,
+    int rows_per_wg) {
+    constexpr int NWV = kFillThreads / kWave;
+    __shared__ uint16_t s_sp[CB];
+    __shared__ uint16_t s_slot[CB];
+    __shared__ uint64_t s_gap[CB];
+    __shared__ uint64_t s_R[NWV][CB];
+    const int j0 = blockIdx.x * CB;
+    const int cnt = min(CB, n - j0);
+    for (int k = threadIdx.x; k < CB; k += kFillThreads) {
+        const bool in = k < cnt;
+        s_sp[k] = in ? blk_sp[j0 + k] : (uint16_t)0xffff;
+        s_slot[k] = in ? blk_slot[j0 + k] : (uint16_t)0;
+        s_gap[k] = in ? blk_gap[j0 + k] : 0ull;
+    }
+    __syncthreads();
+    const int r0 = blockIdx.y * rows_per_wg;
+    const int r1 = min(n, r0 + rows_per_wg);
+    fill_rows_block<CB, WIDEST>(pos, ek, n, j0, cnt, r0, r1, s_sp, s_slot, s_gap,
+                                s_R[threadIdx.x / kWave], M, idx, NWV);
+}
+
+// ---------------------------------------------------------------- launchers
+template <bool WIDEST>
+static hipError_t launch_prim(const float* W, int n, PrimOut out, hipStream_t s) {
+    const int ch = (n + kPrimThreads - 1) / kPrimThreads;
+#define APPD_PRIM_CASE(C)                                                                    \
+    if (ch <= C) {                                                                           \
+        prim_single_kernel<C, WIDEST><<<1, kPrimThreads, 0, s>>>(W, n, out);                 \
+        return hipGetLastError();                                                            \
+    }
+    APPD_PRIM_CASE(1)
+    APPD_PRIM_CASE(2)
+    APPD_PRIM_CASE(4)
+    APPD_PRIM_CASE(8)
+    APPD_PRIM_CASE(16)
+    APPD_PRIM_CASE(24)
+    APPD_PRIM_CASE(32)
+    APPD_PRIM_CASE(46)
+#undef APPD_PRIM_CASE
+    return hipErrorInvalidValue;
+}
+
+int fill_blocks(int n) { return (n + kFillCB - 1) / kFillCB; }
+
+size_t single_workspace_bytes(int n) {
+    const size_t nb = (size_t)fill_blocks(n) * kFillCB;
+    size_t off = 0;
+    off = align_up(off + 4 * (size_t)n);  // order
+    off = align_up(off + 4 * (size_t)n);  // parent
+    off = align_up(off + 4 * (size_t)n);  // pos
+    off = align_up(off + 8 * (size_t)n);  // ek
+    off = align_up(off + 2 * nb);         // blk_sp
+    off = align_up(off + 2 * nb);         // blk_slot
+    off = align_up(off + 8 * nb);         // blk_gap
+    return off;
+}
+
+SingleWs carve_single(void* ws, int n) {
+    const size_t nb = (size_t)fill_blocks(n) * kFillCB;
+    char* b = (char*)ws;
+    SingleWs w;
+    size_t off = 0;
+    w.order = (int32_t*)(b + off);
+    off = align_up(off + 4 * (size_t)n);
+    w.parent = (int32_t*)(b + off);
+    off = align_up(off + 4 * (size_t)n);
+    w.pos = (int32_t*)(b + off);
+    off = align_up(off + 4 * (size_t)n);
+    w.ek = (uint64_t*)(b + off);
+    off = align_up(off + 8 * (size_t)n);
+    w.blk_sp = (uint16_t*)(b + off);
+    off = align_up(off + 2 * nb);
+    w.blk_slot = (uint16_t*)(b + off);
+    off = align_up(off + 2 * nb);
+    w.blk_gap = (uint64_t*)(b + off);
+    return w;
+}
+
+template <bool WIDEST>
+static hipError_t run_single_t(const float* W, int n, float* M, int32_t* idx,
+                               const SingleWs& w, hipStream_t s) {
+    PrimOut out{w.order, w.ek, w.pos, w.parent};
+    hipError_t e = launch_prim<WIDEST>(W, n, out, s);
+    if (e != hipSuccess) return e;
+    const int nb = fill_blocks(n);
+    fill_prep_kernel<kFillCB><<<nb, kFillThreads, 0, s>>>(w.pos, w.ek, n, w.blk_sp, w.blk_slot,
+                                                         w.blk_gap);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    dim3 grid(nb, (n + kFillRowsPerWG - 1) / kFillRowsPerWG);
+    fill_kernel<kFillCB, WIDEST><<<grid, kFillThreads, 0, s>>>(
+        w.pos, w.ek, n, w.blk_sp, w.blk_slot, w.blk_gap, M, idx, kFillRowsPerWG);
+    return hipGetLastError();
+}
+
+hipError_t run_single(const float* W, int n, int mode, float* M, int32_t* idx,
+                      const SingleWs& w, hipStream_t s) {
+    return mode == 1 ? run_single_t<true>(W, n, M, idx, w, s)
+                     : run_single_t<false>(W, n, M, idx, w, s);
+}
+
+}  // namespace appd

@@ -1,0 +1,81 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2407_07058_amd as appd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(appd_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_header_declares_the_core_calls():
+    names = declared_symbols()
+    for n in ("appd_forward", "appd_forward_ws", "appd_forward_ex",
+              "appd_forward_workspace_bytes", "appd_error_string", "appd_get_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(appd.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    # and the Python binding knows every one of them
+    assert declared_symbols() <= set(appd.SIGNATURES)
+
+
+def test_error_strings():
+    L = appd.lib()
+    for c in (0, -1, -2, -3):
+        assert L.appd_error_string(c)
+    assert b"unknown" in L.appd_error_string(7)
+
+
+def test_workspace_bytes():
+    L = appd.lib()
+    assert L.appd_forward_workspace_bytes(0) == 0
+    assert L.appd_forward_workspace_bytes(46341) == 0
+    small = L.appd_forward_workspace_bytes(1)
+    big = L.appd_forward_workspace_bytes(46340)
+    assert 0 < small < big
+    assert big % 256 == 0
+    # O(n): at most a few dozen bytes per vertex
+    assert big < 64 * 46340
+
+
+@pytest.mark.parametrize("n", [0, -5, 46341])
+def test_forward_rejects_bad_n(n):
+    L = appd.lib()
+    p = ctypes.c_void_p(16)
+    assert L.appd_forward(p, n, p, p, None) == appd.APPD_EINVAL
+    assert L.appd_get_last_error() == appd.APPD_EINVAL
+
+
+def test_forward_rejects_null_and_mode():
+    L = appd.lib()
+    p = ctypes.c_void_p(256)
+    assert L.appd_forward(None, 4, p, p, None) == appd.APPD_EINVAL
+    assert L.appd_forward(p, 4, None, p, None) == appd.APPD_EINVAL
+    assert L.appd_forward(p, 4, p, None, None) == appd.APPD_EINVAL
+    assert L.appd_forward_ex(p, 4, 2, p, p, None, None, p, 1 << 20, None) == appd.APPD_EINVAL
+    assert L.appd_forward_ws(p, 4, p, p, None, 0, None) == appd.APPD_EINVAL
+
+
+def test_forward_rejects_small_or_misaligned_workspace():
+    L = appd.lib()
+    p = ctypes.c_void_p(256)
+    need = L.appd_forward_workspace_bytes(100)
+    assert L.appd_forward_ws(p, 100, p, p, p, need - 1, None) == appd.APPD_EINVAL
+    assert L.appd_forward_ws(p, 100, p, p, ctypes.c_void_p(260), need, None) == appd.APPD_EINVAL

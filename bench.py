@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""APPD benchmark on one MI355X.
+
+Workload: one complete graph of n = 8192 points in R^16 drawn from a
+10-component Gaussian mixture (centres uniform in [0,1]^16, sigma 0.05, seed 2);
+float32 Euclidean weights (computed in float64, rounded once), so W is 256 MiB.
+A step is one whole forward -- spanning tree + calculation-and-copy fill --
+writing the float32 M and int32 idx matrices, with W already resident in HBM.
+
+Prints one JSON line: entries/s (n^2 per second) as `value`, the achieved
+algorithmic HBM rate, per-phase times from HIP events recorded on the stream the
+kernels run on, the roofline of the dominant kernel and the CPU oracle timed on
+the host as a reference point.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
+
+
+def source_sha(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {
+    "prim_single_kernel": ["paper_2407_07058_amd/csrc/appd_prim.h",
+                           "paper_2407_07058_amd/csrc/appd_device.h",
+                           "paper_2407_07058_amd/csrc/appd_single.hip"],
+    "fill_kernel": ["paper_2407_07058_amd/csrc/appd_fill.h",
+                    "paper_2407_07058_amd/csrc/appd_device.h",
+                    "paper_2407_07058_amd/csrc/appd_single.hip"],
+}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when it is missing or was taken on a different version of the kernel."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec or rec.get("source_sha") != source_sha(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(W, n, runs=3):
+    import numpy as np
+
+    import oracle
+    ts = []
+    for _ in range(runs):
+        t = time.perf_counter()
+        oracle.appd(W)
+        ts.append(time.perf_counter() - t)
+    t = float(np.median(ts))
+    return {"value": n * n / t, "unit": "entries/s", "cores": 1, "kind": "oracle",
+            "sample": "the full n=%d graph, %d runs of the single-threaded C oracle "
+                      "(plain Algorithm 4), median %.2f s" % (n, runs, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(max(args.steps, 1)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": max(args.steps, 1)}))
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this APPD build runs a graph on a single "
+              "MI355X and has no multi-GPU path (got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2407_07058_amd as appd
+    import workloads
+
+    n = args.n
+    W = workloads.config_mixture(n)
+    dev = torch.device("cuda:0")
+    Wd = torch.from_numpy(W).to(dev)
+    M = torch.empty((n, n), dtype=torch.float32, device=dev)
+    I = torch.empty((n, n), dtype=torch.int32, device=dev)
+    ws = torch.empty(appd.workspace_bytes(n), dtype=torch.uint8, device=dev)
+
+    def step():
+        appd.tree(Wd, ws)
+        appd.fill(n, ws, M, I)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record()
+    for k in range(K):
+        ev[k][0].record()
+        appd.tree(Wd, ws)
+        ev[k][1].record()
+        appd.fill(n, ws, M, I)
+        ev[k][2].record()
+    t_stop.record()
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_stop)
+    ms = total_ms / K
+    tree_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    fill_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+
+    entries = float(n) * n
+    alg_bytes = 12.0 * n * n  # W read + M write + idx write
+    phases = {
+        "tree": {"kernel": "prim_single_kernel", "ms": tree_ms,
+                 "alg_bytes": 4.0 * n * n,
+                 "alg_gbps": 4.0 * n * n / tree_ms / 1e6,
+                 "ns_per_prim_step": tree_ms * 1e6 / max(n - 1, 1)},
+        "fill": {"kernel": "fill_prep_kernel+fill_kernel", "ms": fill_ms,
+                 "alg_bytes": 8.0 * n * n,
+                 "alg_gbps": 8.0 * n * n / fill_ms / 1e6},
+    }
+    dom = "tree" if tree_ms >= fill_ms else "fill"
+    dk = "prim_single_kernel" if dom == "tree" else "fill_kernel"
+    achieved = phases[dom]["alg_gbps"]
+    roofline = {"bound": "hbm", "kernel": dk, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                "traffic": measured_traffic(dk),
+                "alg_bytes_per_launch": phases[dom]["alg_bytes"]}
+
+    out = {
+        "metric": "APPD entries/sec (n^2/s)",
+        "value": entries / (ms / 1e3),
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "single complete graph, n=%d points in R^16 from a "
+                               "10-component Gaussian mixture (sigma 0.05, seed 2); fp32 "
+                               "Euclidean W resident in HBM; outputs fp32 M + int32 idx" % n,
+                   "n": n, "mode": "minimax"},
+        "alg_hbm_gbps": alg_bytes / (ms / 1e3) / 1e9,
+        "phases": phases,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W, n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -89,6 +89,97 @@ int appd_forward_ws(const float* W, int n, float* M, int32_t* idx, void* ws, siz
 int appd_forward_ex(const float* W, int n, int mode, float* M, int32_t* idx, int32_t* order,
                     int32_t* parent, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * The two phases of appd_forward_ex, exposed separately (e.g. to time them).
+ * appd_tree: Prim's spanning tree of W from vertex 0 (Section 3, first step)
+ *   and the attachment order, written into ws (internal layout; ws must
+ *   be >= appd_forward_workspace_bytes(n)).  order / parent as in
+ *   appd_forward_ex (nullable).
+ * appd_fill: M and idx from the tree that appd_tree left in the same ws
+ *   (the calculation-and-copy step of Section 3); same n and mode.
+ */
+int appd_tree(const float* W, int n, int mode, int32_t* order, int32_t* parent, void* ws,
+              size_t ws_bytes, void* stream);
+int appd_fill(int n, int mode, const void* ws, size_t ws_bytes, float* M, int32_t* idx,
+              void* stream);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent graphs of uneven size, packed back to back in graph-id
+ * order: graph g's W, M, idx (and G, dW) occupy n_g^2 elements starting at
+ * element offset sum_{h<g} n_h^2; its O(n) arrays (parent, gradients per
+ * vertex) start at sum_{h<g} n_h; its points X (n_g x d) at d * sum_{h<g} n_h.
+ * Every graph needs 1 <= n_g <= APPD_BATCH_MAX_N.
+ *
+ * appd_batch_prepare plans the batch on the host (size classes, graphs listed
+ * by decreasing n so the longest Prim chains start first, work tables) and
+ * copies the tables into ws with synchronous host-to-device copies; it must
+ * precede the other batch calls and is not capturable in a HIP graph.  The
+ * calls that take a prepared plan only launch kernels on `stream` and can be
+ * captured.  `plan` is plain host data filled by appd_batch_prepare.
+ */
+#define APPD_BATCH_MAX_N 2048
+#define APPD_BATCH_CLASSES 4
+
+typedef struct {
+    int num_graphs;
+    int max_n;
+    int64_t total_n;  /* sum of n_g */
+    int64_t total_nn; /* sum of n_g^2 */
+    int class_first[APPD_BATCH_CLASSES];
+    int class_count[APPD_BATCH_CLASSES];
+    int class_chunks[APPD_BATCH_CLASSES];
+    int pair_tiles;   /* work items of the point-to-graph kernel */
+    int grad_chunks;  /* work items of the edge-gradient kernel */
+    int chain_blocks; /* work items of the point-gradient kernel */
+    size_t ws_bytes;  /* workspace the batch needs */
+} appd_batch_plan;
+
+/* Workspace bytes for a batch with these sizes (0 on invalid input). */
+size_t appd_batch_workspace_bytes(const int32_t* ns_host, int num_graphs);
+
+/* Fill `plan` from the host sizes and upload the device tables into ws. */
+int appd_batch_prepare(const int32_t* ns_host, int num_graphs, void* ws, size_t ws_bytes,
+                       appd_batch_plan* plan, void* stream);
+
+/* Batched forward (Algorithm 4 per graph).  parent: nullable, total_n int32. */
+int appd_forward_batched(const float* W, int mode, float* M, int32_t* idx, int32_t* parent,
+                         const appd_batch_plan* plan, void* ws, void* stream);
+
+/* Complete graphs from packed point sets: W_ij = sqrt(sum_t (x_it - x_jt)^2),
+ * summed in increasing t, each operation rounded once (bit-symmetric).
+ * 1 <= d <= APPD_MAX_DIM. */
+#define APPD_MAX_DIM 64
+int appd_pairwise_euclidean_batched(const float* X, int d, float* W, const appd_batch_plan* plan,
+                                    void* ws, void* stream);
+
+/*
+ * Backward of L = sum_{i != j} G_ij M_ij for point inputs, per graph:
+ * dL/dw(e) = sum of G_ij over pairs whose bottleneck edge is e; then through
+ * w = ||x_u - x_v||: dX_u += g (x_u - x_v)/w, dX_v -= g (x_u - x_v)/w.  W, idx and
+ * parent are those of the forward; dX (total_n x d) is overwritten.  Float
+ * atomics: the summation order, hence the last bits, vary between runs.
+ */
+int appd_backward_points_batched(const float* X, int d, const float* W, const float* G,
+                                 const int32_t* idx, const int32_t* parent, float* dX,
+                                 const appd_batch_plan* plan, void* ws, void* stream);
+
+/* ------------------------------------------------------------------ single
+ * Single-graph forms of the two calls above.  ws: >= appd_grad_workspace_bytes(n)
+ * device bytes (256-byte aligned).  n <= APPD_GRAD_MAX_N for the backward. */
+#define APPD_GRAD_MAX_N 32768
+size_t appd_grad_workspace_bytes(int n);
+int appd_pairwise_euclidean(const float* X, int n, int d, float* W, void* ws, size_t ws_bytes,
+                            void* stream);
+int appd_backward_points(const float* X, int n, int d, const float* W, const float* G,
+                         const int32_t* idx, const int32_t* parent, float* dX, void* ws,
+                         size_t ws_bytes, void* stream);
+
+/* Backward for a weight-matrix input: dW[idx(i,j)] += G_ij for i != j, i.e. every
+ * pair's gradient goes to the upper-triangle entry (u < v) of its bottleneck
+ * edge.  dW (n x n) is overwritten (zero except on tree edges). */
+int appd_backward_w(const float* G, const int32_t* idx, const int32_t* parent, int n, float* dW,
+                    void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,6 +14,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -39,7 +40,32 @@ SIGNATURES = {
     "appd_forward": ([_P, _I, _P, _P, _P], _I),
     "appd_forward_ws": ([_P, _I, _P, _P, _P, _SZ, _P], _I),
     "appd_forward_ex": ([_P, _I, _I, _P, _P, _P, _P, _P, _SZ, _P], _I),
+    "appd_tree": ([_P, _I, _I, _P, _P, _P, _SZ, _P], _I),
+    "appd_fill": ([_I, _I, _P, _SZ, _P, _P, _P], _I),
+    "appd_batch_workspace_bytes": ([_P, _I], _SZ),
+    "appd_batch_prepare": ([_P, _I, _P, _SZ, _P, _P], _I),
+    "appd_forward_batched": ([_P, _I, _P, _P, _P, _P, _P, _P], _I),
+    "appd_pairwise_euclidean_batched": ([_P, _I, _P, _P, _P, _P], _I),
+    "appd_backward_points_batched": ([_P, _I, _P, _P, _P, _P, _P, _P, _P, _P], _I),
+    "appd_grad_workspace_bytes": ([_I], _SZ),
+    "appd_pairwise_euclidean": ([_P, _I, _I, _P, _P, _SZ, _P], _I),
+    "appd_backward_points": ([_P, _I, _I, _P, _P, _P, _P, _P, _P, _SZ, _P], _I),
+    "appd_backward_w": ([_P, _P, _P, _I, _P, _P, _SZ, _P], _I),
 }
+
+BATCH_MAX_N = 2048
+MAX_DIM = 64
+GRAD_MAX_N = 32768
+
+
+class BatchPlan(ctypes.Structure):
+    """Mirror of appd_batch_plan (include/appd.h)."""
+    _fields_ = [("num_graphs", ctypes.c_int), ("max_n", ctypes.c_int),
+                ("total_n", ctypes.c_int64), ("total_nn", ctypes.c_int64),
+                ("class_first", ctypes.c_int * 4), ("class_count", ctypes.c_int * 4),
+                ("class_chunks", ctypes.c_int * 4), ("pair_tiles", ctypes.c_int),
+                ("grad_chunks", ctypes.c_int), ("chain_blocks", ctypes.c_int),
+                ("ws_bytes", ctypes.c_size_t)]
 
 _lib = None
 
@@ -125,3 +151,186 @@ def forward(W: torch.Tensor, mode: int = MINIMAX, return_tree: bool = False, out
     if return_tree:
         return M, idx, order, parent
     return M, idx
+
+
+def tree(W: torch.Tensor, workspace: torch.Tensor, mode: int = MINIMAX):
+    """Phase 1 only: spanning tree and attachment order into `workspace`."""
+    n = _check_square(W)
+    _check(lib().appd_tree(_ptr(W), n, int(mode), None, None, _ptr(workspace),
+                           workspace.numel(), _stream(W.device)), "appd_tree")
+
+
+def fill(n: int, workspace: torch.Tensor, M: torch.Tensor, idx: torch.Tensor,
+         mode: int = MINIMAX):
+    """Phase 2 only: M and idx from the tree `tree()` left in `workspace`."""
+    _check(lib().appd_fill(int(n), int(mode), _ptr(workspace), workspace.numel(), _ptr(M),
+                           _ptr(idx), _stream(M.device)), "appd_fill")
+
+
+# ------------------------------------------------------------------ batches
+class Batch:
+    """A prepared batch of independent graphs with sizes `ns` (host ints).
+
+    Packed layout (graph-id order): graph g's n_g x n_g matrices start at
+    ``offsets[g] = sum_{h<g} n_h^2`` elements, its per-vertex arrays at
+    ``noff[g] = sum_{h<g} n_h`` and its points (n_g x d) at ``d * noff[g]``.
+    """
+
+    def __init__(self, ns, device="cuda:0"):
+        self.ns = np.ascontiguousarray(ns, dtype=np.int32)
+        if self.ns.ndim != 1 or len(self.ns) < 1:
+            raise ValueError("ns must be a non-empty 1-D sequence")
+        if (self.ns < 1).any() or (self.ns > BATCH_MAX_N).any():
+            raise ValueError("every n must be in [1, %d]" % BATCH_MAX_N)
+        self.device = torch.device(device)
+        self.G = len(self.ns)
+        sq = self.ns.astype(np.int64) ** 2
+        self.offsets = np.concatenate([[0], np.cumsum(sq)[:-1]]).astype(np.int64)
+        self.noff = np.concatenate([[0], np.cumsum(self.ns.astype(np.int64))[:-1]]).astype(np.int64)
+        self.total_nn = int(sq.sum())
+        self.total_n = int(self.ns.astype(np.int64).sum())
+        nbytes = int(lib().appd_batch_workspace_bytes(self.ns.ctypes.data_as(_P), self.G))
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.plan = BatchPlan()
+        _check(lib().appd_batch_prepare(self.ns.ctypes.data_as(_P), self.G, _ptr(self.ws), nbytes,
+                                        ctypes.byref(self.plan), _stream(self.device)),
+               "appd_batch_prepare")
+
+    def forward(self, W: torch.Tensor, mode: int = MINIMAX, return_parent: bool = False,
+                out=None):
+        """Packed (M, idx[, parent]) of every graph of the batch."""
+        if W.dtype != torch.float32 or W.numel() != self.total_nn or not W.is_contiguous():
+            raise ValueError("W must be a contiguous float32 tensor of sum(n^2) elements")
+        if out is None:
+            M = torch.empty(self.total_nn, dtype=torch.float32, device=self.device)
+            idx = torch.empty(self.total_nn, dtype=torch.int32, device=self.device)
+        else:
+            M, idx = out
+        parent = torch.empty(self.total_n, dtype=torch.int32, device=self.device) \
+            if return_parent else None
+        _check(lib().appd_forward_batched(_ptr(W), int(mode), _ptr(M), _ptr(idx), _ptr(parent),
+                                          ctypes.byref(self.plan), _ptr(self.ws),
+                                          _stream(self.device)), "appd_forward_batched")
+        return (M, idx, parent) if return_parent else (M, idx)
+
+    def pairwise(self, X: torch.Tensor, d: int, out: torch.Tensor = None) -> torch.Tensor:
+        """Packed Euclidean W of the batch's point sets (X: total_n x d float32)."""
+        if X.dtype != torch.float32 or X.numel() != self.total_n * d or not X.is_contiguous():
+            raise ValueError("X must be a contiguous float32 tensor of total_n * d elements")
+        W = out if out is not None else torch.empty(self.total_nn, dtype=torch.float32,
+                                                     device=self.device)
+        _check(lib().appd_pairwise_euclidean_batched(_ptr(X), int(d), _ptr(W),
+                                                     ctypes.byref(self.plan), _ptr(self.ws),
+                                                     _stream(self.device)),
+               "appd_pairwise_euclidean_batched")
+        return W
+
+    def backward_points(self, X, d, W, G, idx, parent) -> torch.Tensor:
+        dX = torch.empty(self.total_n * d, dtype=torch.float32, device=self.device)
+        _check(lib().appd_backward_points_batched(_ptr(X), int(d), _ptr(W), _ptr(G), _ptr(idx),
+                                                  _ptr(parent), _ptr(dX), ctypes.byref(self.plan),
+                                                  _ptr(self.ws), _stream(self.device)),
+               "appd_backward_points_batched")
+        return dX
+
+
+# ------------------------------------------------------------------ points, gradients
+def _grad_ws(n, dev):
+    return torch.empty(int(lib().appd_grad_workspace_bytes(int(n))), dtype=torch.uint8, device=dev)
+
+
+def pairwise_euclidean(X: torch.Tensor) -> torch.Tensor:
+    """W_ij = ||x_i - x_j||, float32, summed in increasing coordinate order."""
+    if X.dtype != torch.float32 or X.dim() != 2 or not X.is_cuda or not X.is_contiguous():
+        raise ValueError("X must be a contiguous float32 CUDA matrix")
+    n, d = X.shape
+    W = torch.empty((n, n), dtype=torch.float32, device=X.device)
+    ws = _grad_ws(n, X.device)
+    _check(lib().appd_pairwise_euclidean(_ptr(X), n, d, _ptr(W), _ptr(ws), ws.numel(),
+                                         _stream(X.device)), "appd_pairwise_euclidean")
+    return W
+
+
+def backward_points(X, W, G, idx, parent) -> torch.Tensor:
+    n, d = X.shape
+    dX = torch.empty((n, d), dtype=torch.float32, device=X.device)
+    ws = _grad_ws(n, X.device)
+    _check(lib().appd_backward_points(_ptr(X), n, d, _ptr(W), _ptr(G), _ptr(idx), _ptr(parent),
+                                      _ptr(dX), _ptr(ws), ws.numel(), _stream(X.device)),
+           "appd_backward_points")
+    return dX
+
+
+def backward_w(G, idx, parent) -> torch.Tensor:
+    n = G.shape[0]
+    dW = torch.empty((n, n), dtype=torch.float32, device=G.device)
+    ws = _grad_ws(n, G.device)
+    _check(lib().appd_backward_w(_ptr(G), _ptr(idx), _ptr(parent), n, _ptr(dW), _ptr(ws),
+                                 ws.numel(), _stream(G.device)), "appd_backward_w")
+    return dW
+
+
+class APPDPoints(torch.autograd.Function):
+    """M = APPD(||x_i - x_j||) for one point set; idx is returned, not differentiated."""
+
+    @staticmethod
+    def forward(ctx, X):
+        X = X.contiguous()
+        W = pairwise_euclidean(X)
+        M, idx, _, parent = forward(W, return_tree=True)
+        ctx.save_for_backward(X, W, idx, parent)
+        ctx.mark_non_differentiable(idx)
+        return M, idx
+
+    @staticmethod
+    def backward(ctx, gM, gidx):
+        X, W, idx, parent = ctx.saved_tensors
+        return backward_points(X, W, gM.contiguous(), idx, parent)
+
+
+class APPDWeights(torch.autograd.Function):
+    """M = APPD(W) for a weight matrix; the gradient goes to the upper-triangle
+    entry of each pair's bottleneck edge."""
+
+    @staticmethod
+    def forward(ctx, W):
+        W = W.contiguous()
+        M, idx, _, parent = forward(W, return_tree=True)
+        ctx.save_for_backward(idx, parent)
+        ctx.mark_non_differentiable(idx)
+        return M, idx
+
+    @staticmethod
+    def backward(ctx, gM, gidx):
+        idx, parent = ctx.saved_tensors
+        return backward_w(gM.contiguous(), idx, parent)
+
+
+class APPDPointsBatched(torch.autograd.Function):
+    """Packed M of a batch of point sets (X: total_n x d float32, packed)."""
+
+    @staticmethod
+    def forward(ctx, X, batch, d):
+        X = X.contiguous()
+        W = batch.pairwise(X, d)
+        M, idx, parent = batch.forward(W, return_parent=True)
+        ctx.save_for_backward(X, W, idx, parent)
+        ctx.batch = batch
+        ctx.d = d
+        ctx.mark_non_differentiable(idx)
+        return M, idx
+
+    @staticmethod
+    def backward(ctx, gM, gidx):
+        X, W, idx, parent = ctx.saved_tensors
+        dX = ctx.batch.backward_points(X, ctx.d, W, gM.contiguous(), idx, parent)
+        return dX.view_as(X), None, None
+
+
+def appd_points(X: torch.Tensor):
+    """Differentiable APPD of a point set: (M, idx)."""
+    return APPDPoints.apply(X)
+
+
+def appd_points_batched(X: torch.Tensor, batch: Batch, d: int):
+    return APPDPointsBatched.apply(X, batch, d)

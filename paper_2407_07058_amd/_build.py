@@ -9,10 +9,12 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libappd.so")
 
-SOURCES = ["appd_api.hip", "appd_single.hip"]
+SOURCES = ["appd_api.hip", "appd_api_batch.hip", "appd_single.hip", "appd_batched.hip", "appd_grad.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # every float operation rounded on its own (results are compared bit for bit)
+    "-ffp-contract=off",
     # no packed-FP32 instructions anywhere in this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

@@ -21,6 +21,10 @@ bool bad_n(int n) { return n < 1 || n > APPD_MAX_N; }
 
 }  // namespace
 
+namespace appd {
+void set_last_error(int code) { g_last = code; }
+}  // namespace appd
+
 extern "C" {
 
 const char* appd_error_string(int code) {
@@ -77,6 +81,32 @@ int appd_forward_ws(const float* W, int n, float* M, int32_t* idx, void* ws, siz
 
 int appd_forward(const float* W, int n, float* M, int32_t* idx, void* stream) {
     return appd_forward_ex(W, n, APPD_MINIMAX, M, idx, nullptr, nullptr, nullptr, 0, stream);
+}
+
+int appd_tree(const float* W, int n, int mode, int32_t* order, int32_t* parent, void* ws,
+              size_t ws_bytes, void* stream) {
+    if (bad_n(n) || !W || !ws || (mode != APPD_MINIMAX && mode != APPD_WIDEST)) return fail(APPD_EINVAL);
+    if (ws_bytes < appd::single_workspace_bytes(n) || ((uintptr_t)ws & 255u)) return fail(APPD_EINVAL);
+    appd::SingleWs w = appd::carve_single(ws, n);
+    if (order) w.order = order;
+    if (parent) w.parent = parent;
+    if (appd::run_tree(W, n, mode, w, (hipStream_t)stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(APPD_EHIP);
+    }
+    return ok();
+}
+
+int appd_fill(int n, int mode, const void* ws, size_t ws_bytes, float* M, int32_t* idx,
+              void* stream) {
+    if (bad_n(n) || !ws || !M || !idx || (mode != APPD_MINIMAX && mode != APPD_WIDEST)) return fail(APPD_EINVAL);
+    if (ws_bytes < appd::single_workspace_bytes(n) || ((uintptr_t)ws & 255u)) return fail(APPD_EINVAL);
+    appd::SingleWs w = appd::carve_single(const_cast<void*>(ws), n);
+    if (appd::run_fill(n, mode, M, idx, w, (hipStream_t)stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(APPD_EHIP);
+    }
+    return ok();
 }
 
 }  // extern "C"

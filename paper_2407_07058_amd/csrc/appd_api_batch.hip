@@ -1,0 +1,309 @@
+// C ABI of the batched and gradient calls (include/appd.h): host planning,
+// workspace carving, argument checks.  All compute runs in the kernels.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "appd.h"
+#include "appd_internal.h"
+
+namespace {
+
+int fail(int code) {
+    appd::set_last_error(code);
+    return code;
+}
+
+int ok() {
+    appd::set_last_error(APPD_OK);
+    return APPD_OK;
+}
+
+// Device tables of a batch, at the start of its workspace.
+struct Tables {
+    int32_t* ns;
+    int64_t* offsets;
+    int64_t* noff;
+    int64_t* xoff;
+    int32_t* perm;
+    int32_t* chunk_start;
+    int32_t* tile_start;
+    int32_t* gchunk_start;
+    int32_t* vstart;
+    // tree and gradient scratch
+    int32_t* order;
+    int32_t* parent;
+    int32_t* pos;
+    uint64_t* ek;
+    float* gedge;
+    size_t table_bytes;  // bytes of the region uploaded by prepare
+    size_t total_bytes;
+};
+
+Tables carve(void* ws, int G, int64_t total_n) {
+    using appd::align_up;
+    char* b = (char*)ws;
+    Tables t;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = b + off;
+        off = align_up(off + bytes);
+        return p;
+    };
+    t.ns = (int32_t*)take(4 * (size_t)G);
+    t.offsets = (int64_t*)take(8 * (size_t)G);
+    t.noff = (int64_t*)take(8 * (size_t)G);
+    t.perm = (int32_t*)take(4 * (size_t)G);
+    t.chunk_start = (int32_t*)take(4 * (size_t)G);
+    t.tile_start = (int32_t*)take(4 * (size_t)G);
+    t.gchunk_start = (int32_t*)take(4 * (size_t)G);
+    t.vstart = (int32_t*)take(4 * (size_t)G);
+    t.table_bytes = off;
+    t.xoff = (int64_t*)take(8 * (size_t)G);
+    t.order = (int32_t*)take(4 * (size_t)total_n);
+    t.parent = (int32_t*)take(4 * (size_t)total_n);
+    t.pos = (int32_t*)take(4 * (size_t)total_n);
+    t.ek = (uint64_t*)take(8 * (size_t)total_n);
+    t.gedge = (float*)take(4 * (size_t)total_n);
+    t.total_bytes = off;
+    return t;
+}
+
+bool sizes_ok(const int32_t* ns, int G, int64_t* total_n) {
+    if (!ns || G < 1) return false;
+    int64_t tn = 0;
+    for (int g = 0; g < G; ++g) {
+        if (ns[g] < 1 || ns[g] > APPD_BATCH_MAX_N) return false;
+        tn += ns[g];
+    }
+    *total_n = tn;
+    return true;
+}
+
+bool plan_ok(const appd_batch_plan* p, const void* ws) {
+    return p && ws && p->num_graphs >= 1 && p->ws_bytes > 0 && ((uintptr_t)ws & 255u) == 0;
+}
+
+appd::BatchPlan device_plan(const appd_batch_plan* p, const Tables& t) {
+    appd::BatchPlan bp;
+    bp.perm = t.perm;
+    bp.noff = t.noff;
+    bp.chunk_start = t.chunk_start;
+    for (int c = 0; c < appd::kBatchClasses; ++c) {
+        bp.class_first[c] = p->class_first[c];
+        bp.class_count[c] = p->class_count[c];
+        bp.class_chunks[c] = p->class_chunks[c];
+    }
+    return bp;
+}
+
+int hip_status(hipError_t e) {
+    if (e == hipSuccess) return ok();
+    (void)hipGetLastError();
+    return fail(APPD_EHIP);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t appd_batch_workspace_bytes(const int32_t* ns_host, int num_graphs) {
+    int64_t tn;
+    if (!sizes_ok(ns_host, num_graphs, &tn)) return 0;
+    return carve(nullptr, num_graphs, tn).total_bytes;
+}
+
+int appd_batch_prepare(const int32_t* ns_host, int num_graphs, void* ws, size_t ws_bytes,
+                       appd_batch_plan* plan, void* stream) {
+    int64_t tn;
+    if (!plan || !ws || ((uintptr_t)ws & 255u) || !sizes_ok(ns_host, num_graphs, &tn))
+        return fail(APPD_EINVAL);
+    const int G = num_graphs;
+    Tables lay = carve(nullptr, G, tn);
+    if (ws_bytes < lay.total_bytes) return fail(APPD_EINVAL);
+
+    appd_batch_plan p;
+    std::memset(&p, 0, sizeof(p));
+    p.num_graphs = G;
+    p.total_n = tn;
+    p.ws_bytes = lay.total_bytes;
+    std::vector<int32_t> perm(G);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(),
+                     [&](int a, int b) { return ns_host[a] > ns_host[b]; });
+    std::vector<int64_t> offsets(G), noff(G);
+    std::vector<int32_t> chunk_start(G), tile_start(G), gchunk_start(G), vstart(G);
+    int64_t o = 0, no = 0;
+    int64_t tiles = 0, gch = 0, vb = 0;
+    const int tile = appd::pairwise_tile();
+    for (int g = 0; g < G; ++g) {
+        const int64_t n = ns_host[g];
+        offsets[g] = o;
+        noff[g] = no;
+        tile_start[g] = (int32_t)tiles;
+        gchunk_start[g] = (int32_t)gch;
+        vstart[g] = (int32_t)vb;
+        o += n * n;
+        no += n;
+        const int64_t nt = (n + tile - 1) / tile;
+        tiles += nt * nt;
+        gch += (n + appd::kGradRows - 1) / appd::kGradRows;
+        vb += (n + appd::kChainThreads - 1) / appd::kChainThreads;
+        p.max_n = std::max(p.max_n, (int)n);
+    }
+    if (tiles > INT32_MAX || gch > INT32_MAX || vb > INT32_MAX) return fail(APPD_EINVAL);
+    p.total_nn = o;
+    p.pair_tiles = (int)tiles;
+    p.grad_chunks = (int)gch;
+    p.chain_blocks = (int)vb;
+    // classes are contiguous in perm (n descending, class ascending in n)
+    for (int c = 0; c < appd::kBatchClasses; ++c) p.class_first[c] = -1;
+    const int rows = appd::batch_rows_per_chunk();
+    for (int i = 0; i < G; ++i) {
+        const int n = ns_host[perm[i]];
+        const int c = appd::batch_class_of(n);
+        if (p.class_first[c] < 0) p.class_first[c] = i;
+        p.class_count[c]++;
+        chunk_start[i] = p.class_chunks[c];
+        p.class_chunks[c] += (n + rows - 1) / rows;
+    }
+    for (int c = 0; c < appd::kBatchClasses; ++c)
+        if (p.class_first[c] < 0) p.class_first[c] = 0;
+
+    // one host image of the table region, one synchronous copy
+    std::vector<char> img(lay.table_bytes, 0);
+    Tables h = carve(img.data(), G, tn);
+    std::memcpy(h.ns, ns_host, 4 * (size_t)G);
+    std::memcpy(h.offsets, offsets.data(), 8 * (size_t)G);
+    std::memcpy(h.noff, noff.data(), 8 * (size_t)G);
+    std::memcpy(h.perm, perm.data(), 4 * (size_t)G);
+    std::memcpy(h.chunk_start, chunk_start.data(), 4 * (size_t)G);
+    std::memcpy(h.tile_start, tile_start.data(), 4 * (size_t)G);
+    std::memcpy(h.gchunk_start, gchunk_start.data(), 4 * (size_t)G);
+    std::memcpy(h.vstart, vstart.data(), 4 * (size_t)G);
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(ws, img.data(), lay.table_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(APPD_EHIP);
+    }
+    *plan = p;
+    return ok();
+}
+
+int appd_forward_batched(const float* W, int mode, float* M, int32_t* idx, int32_t* parent,
+                         const appd_batch_plan* plan, void* ws, void* stream) {
+    if (!W || !M || !idx || !plan_ok(plan, ws) || (mode != APPD_MINIMAX && mode != APPD_WIDEST))
+        return fail(APPD_EINVAL);
+    Tables t = carve(ws, plan->num_graphs, plan->total_n);
+    appd::BatchTree tree{t.order, t.ek, t.pos, parent ? parent : t.parent};
+    appd::BatchPlan bp = device_plan(plan, t);
+    return hip_status(appd::run_batched(W, t.offsets, t.ns, bp, tree, mode, M, idx,
+                                        (hipStream_t)stream));
+}
+
+int appd_pairwise_euclidean_batched(const float* X, int d, float* W, const appd_batch_plan* plan,
+                                    void* ws, void* stream) {
+    if (!X || !W || !plan_ok(plan, ws) || d < 1 || d > APPD_MAX_DIM) return fail(APPD_EINVAL);
+    Tables t = carve(ws, plan->num_graphs, plan->total_n);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = appd::run_scale_offsets(t.noff, plan->num_graphs, d, t.xoff, s);
+    if (e == hipSuccess)
+        e = appd::run_pairwise(X, t.xoff, t.offsets, t.ns, t.tile_start, plan->num_graphs,
+                               plan->pair_tiles, d, W, s);
+    return hip_status(e);
+}
+
+int appd_backward_points_batched(const float* X, int d, const float* W, const float* G,
+                                 const int32_t* idx, const int32_t* parent, float* dX,
+                                 const appd_batch_plan* plan, void* ws, void* stream) {
+    if (!X || !W || !G || !idx || !parent || !dX || !plan_ok(plan, ws) || d < 1 ||
+        d > APPD_MAX_DIM)
+        return fail(APPD_EINVAL);
+    Tables t = carve(ws, plan->num_graphs, plan->total_n);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = appd::run_zero(t.gedge, 4 * (size_t)plan->total_n, s);
+    if (e == hipSuccess) e = appd::run_zero(dX, 4 * (size_t)plan->total_n * d, s);
+    if (e == hipSuccess) e = appd::run_scale_offsets(t.noff, plan->num_graphs, d, t.xoff, s);
+    if (e == hipSuccess)
+        e = appd::run_edge_grad(G, idx, t.offsets, t.noff, t.ns, parent, t.gchunk_start,
+                                plan->num_graphs, plan->grad_chunks, appd::kGradRows, plan->max_n,
+                                t.gedge, s);
+    if (e == hipSuccess)
+        e = appd::run_chain(X, t.xoff, W, t.offsets, t.noff, t.ns, parent, t.gedge, t.vstart,
+                            plan->num_graphs, plan->chain_blocks, d, dX, s);
+    return hip_status(e);
+}
+
+// ---- single-graph forms: a one-graph table written by a kernel (capture-safe)
+size_t appd_grad_workspace_bytes(int n) {
+    if (n < 1 || n > APPD_MAX_N) return 0;
+    return carve(nullptr, 1, n).total_bytes;
+}
+
+static int single_tables(int n, void* ws, size_t ws_bytes, Tables* t, hipStream_t s) {
+    if (!ws || ((uintptr_t)ws & 255u) || ws_bytes < appd_grad_workspace_bytes(n)) return APPD_EINVAL;
+    *t = carve(ws, 1, n);
+    if (appd::run_single_table(n, t->ns, t->offsets, t->noff, t->tile_start, t->gchunk_start,
+                               t->vstart, s) != hipSuccess)
+        return APPD_EHIP;
+    return APPD_OK;
+}
+
+int appd_pairwise_euclidean(const float* X, int n, int d, float* W, void* ws, size_t ws_bytes,
+                            void* stream) {
+    if (!X || !W || n < 1 || n > APPD_MAX_N || d < 1 || d > APPD_MAX_DIM) return fail(APPD_EINVAL);
+    hipStream_t s = (hipStream_t)stream;
+    Tables t;
+    int rc = single_tables(n, ws, ws_bytes, &t, s);
+    if (rc != APPD_OK) return rc == APPD_EHIP ? hip_status(hipErrorUnknown) : fail(rc);
+    const int64_t nt = (n + appd::pairwise_tile() - 1) / appd::pairwise_tile();
+    hipError_t e = appd::run_scale_offsets(t.noff, 1, d, t.xoff, s);
+    if (e == hipSuccess)
+        e = appd::run_pairwise(X, t.xoff, t.offsets, t.ns, t.tile_start, 1, (int)(nt * nt), d, W, s);
+    return hip_status(e);
+}
+
+int appd_backward_points(const float* X, int n, int d, const float* W, const float* G,
+                         const int32_t* idx, const int32_t* parent, float* dX, void* ws,
+                         size_t ws_bytes, void* stream) {
+    if (!X || !W || !G || !idx || !parent || !dX || n < 1 || n > APPD_GRAD_MAX_N || d < 1 ||
+        d > APPD_MAX_DIM)
+        return fail(APPD_EINVAL);
+    hipStream_t s = (hipStream_t)stream;
+    Tables t;
+    int rc = single_tables(n, ws, ws_bytes, &t, s);
+    if (rc != APPD_OK) return rc == APPD_EHIP ? hip_status(hipErrorUnknown) : fail(rc);
+    const int chunks = (n + appd::kGradRows - 1) / appd::kGradRows;
+    const int vblocks = (n + appd::kChainThreads - 1) / appd::kChainThreads;
+    hipError_t e = appd::run_zero(t.gedge, 4 * (size_t)n, s);
+    if (e == hipSuccess) e = appd::run_zero(dX, 4 * (size_t)n * d, s);
+    if (e == hipSuccess) e = appd::run_scale_offsets(t.noff, 1, d, t.xoff, s);
+    if (e == hipSuccess)
+        e = appd::run_edge_grad(G, idx, t.offsets, t.noff, t.ns, parent, t.gchunk_start, 1,
+                                chunks, appd::kGradRows, n, t.gedge, s);
+    if (e == hipSuccess)
+        e = appd::run_chain(X, t.xoff, W, t.offsets, t.noff, t.ns, parent, t.gedge, t.vstart, 1,
+                            vblocks, d, dX, s);
+    return hip_status(e);
+}
+
+int appd_backward_w(const float* G, const int32_t* idx, const int32_t* parent, int n, float* dW,
+                    void* ws, size_t ws_bytes, void* stream) {
+    if (!G || !idx || !parent || !dW || n < 1 || n > APPD_GRAD_MAX_N) return fail(APPD_EINVAL);
+    hipStream_t s = (hipStream_t)stream;
+    Tables t;
+    int rc = single_tables(n, ws, ws_bytes, &t, s);
+    if (rc != APPD_OK) return rc == APPD_EHIP ? hip_status(hipErrorUnknown) : fail(rc);
+    const int chunks = (n + appd::kGradRows - 1) / appd::kGradRows;
+    hipError_t e = appd::run_zero(t.gedge, 4 * (size_t)n, s);
+    if (e == hipSuccess) e = appd::run_zero(dW, 4 * (size_t)n * n, s);
+    if (e == hipSuccess)
+        e = appd::run_edge_grad(G, idx, t.offsets, t.noff, t.ns, parent, t.gchunk_start, 1,
+                                chunks, appd::kGradRows, n, t.gedge, s);
+    if (e == hipSuccess) e = appd::run_edge_to_w(t.gedge, parent, n, dW, s);
+    return hip_status(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,285 @@
+// Points -> complete graph, and the backward pass of the APPD selection.
+//
+// pairwise: W_ij = sqrt(sum_{t < d} (x_it - x_jt)^2), the sum taken in
+//   increasing t with every subtraction, product, sum and the square root
+//   rounded once (no contraction), so W is bit-symmetric and reproducible.
+//   (Section 1: a dataset is turned into a complete graph; the paper does not
+//   name the metric, Euclidean is the reading taken here.)  64 x 64 output tiles,
+//   one workgroup each, the two point blocks staged in LDS.
+//
+// backward: with L = sum_{i != j} G_ij M_ij and M_ij the weight of the
+//   bottleneck edge idx(i,j), dL/dw(e) = sum of G_ij over the pairs whose
+//   bottleneck is e.  An edge (u,v) of the rooted spanning tree is stored at the
+//   slot of its child endpoint (parent[child] == other end).  Each workgroup
+//   accumulates a block of rows into an LDS histogram over the slots, then adds
+//   its non-zero bins to the global per-edge sums.  The chain rule through
+//   w = ||x_c - x_p|| then moves g * (x_c - x_p) / w to x_c and its negative to
+//   x_p.  Float atomics make the summation order vary between runs.
+#include "appd_device.h"
+#include "appd_internal.h"
+
+// Every product and sum below is rounded on its own (no fused multiply-add).
+#pragma clang fp contract(off)
+
+namespace appd {
+
+constexpr int kTile = 64;
+constexpr int kPairThreads = 256;
+constexpr int kMaxD = 64;
+
+// Locate work item b in a per-graph prefix table (last gi with start[gi] <= b).
+__device__ __forceinline__ int find_item(const int32_t* __restrict__ start, int count, int b) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Correctly rounded float square root of x >= 0.  A hardware estimate s is
+// moved to its neighbour while sqrt(x) lies beyond the midpoint between them:
+// a midpoint of two adjacent floats has at most 25 significant bits, so its
+// square is exact in double and the comparison with x is exact.  (No tie is
+// possible: the square of such a midpoint needs more than 24 bits.)  Subnormal
+// inputs are scaled by 2^24 first (exact), the root then by 2^-12 (exact).
+__device__ __forceinline__ float sqrt_rn_exact(float x) {
+    if (!(x > 0.0f) || x == __builtin_inff()) return x == 0.0f ? 0.0f : __builtin_sqrtf(x);
+    const bool sub = x < 1.17549435e-38f;
+    if (sub) x *= 16777216.0f;
+    float s = __builtin_sqrtf(x);
+    const double xd = (double)x;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const float up = __uint_as_float(__float_as_uint(s) + 1u);
+        const double mu = ((double)s + (double)up) * 0.5;
+        if (mu * mu < xd) {
+            s = up;
+            continue;
+        }
+        const float dn = __uint_as_float(__float_as_uint(s) - 1u);
+        const double md = ((double)s + (double)dn) * 0.5;
+        if (md * md > xd) s = dn;
+    }
+    return sub ? s * 2.44140625e-4f : s;
+}
+
+__global__ __launch_bounds__(kPairThreads) void pairwise_kernel(
+    const float* __restrict__ X, const int64_t* __restrict__ xoff,
+    const int64_t* __restrict__ offsets, const int32_t* __restrict__ ns,
+    const int32_t* __restrict__ tile_start, int num_graphs, int d, float* __restrict__ W) {
+    __shared__ float xi[kTile][kMaxD + 1];
+    __shared__ float xjT[kMaxD][kTile + 1];
+    const int g = find_item(tile_start, num_graphs, blockIdx.x);
+    const int n = ns[g];
+    const int nt = (n + kTile - 1) / kTile;
+    const int tile = blockIdx.x - tile_start[g];
+    const int ti = tile / nt, tj = tile % nt;
+    const float* Xg = X + xoff[g];
+    float* Wg = W + offsets[g];
+    const int i0 = ti * kTile, j0 = tj * kTile;
+    for (int e = threadIdx.x; e < kTile * d; e += kPairThreads) {
+        const int r = e / d, t = e % d;
+        xi[r][t] = (i0 + r < n) ? Xg[(size_t)(i0 + r) * d + t] : 0.0f;
+        xjT[t][r] = (j0 + r < n) ? Xg[(size_t)(j0 + r) * d + t] : 0.0f;
+    }
+    __syncthreads();
+    const int c = threadIdx.x & (kTile - 1);
+    const int j = j0 + c;
+    for (int r = threadIdx.x / kTile; r < kTile; r += kPairThreads / kTile) {
+        const int i = i0 + r;
+        if (i >= n || j >= n) continue;
+        float acc = 0.0f;
+        for (int t = 0; t < d; ++t) {
+            const float df = __fsub_rn(xi[r][t], xjT[t][c]);
+            acc = __fadd_rn(acc, __fmul_rn(df, df));
+        }
+        Wg[(size_t)i * n + j] = (i == j) ? 0.0f : sqrt_rn_exact(acc);
+    }
+}
+
+// Slot of the tree edge with flat index e = u*n + v (u < v).
+__device__ __forceinline__ int edge_slot(uint32_t e, uint32_t n, double inv_n,
+                                         const int32_t* __restrict__ parent) {
+    int64_t q = (int64_t)((double)e * inv_n);
+    int64_t r = (int64_t)e - q * (int64_t)n;
+    if (r < 0) { --q; r += n; }
+    if (r >= (int64_t)n) { ++q; r -= n; }
+    const int u = (int)q, v = (int)r;
+    return parent[v] == u ? v : u;
+}
+
+// One workgroup: rows [r0, r1) of one graph; hist holds n floats of LDS.
+__global__ __launch_bounds__(256) void edge_grad_kernel(
+    const float* __restrict__ G, const int32_t* __restrict__ idx,
+    const int64_t* __restrict__ offsets, const int64_t* __restrict__ noff,
+    const int32_t* __restrict__ ns, const int32_t* __restrict__ parent,
+    const int32_t* __restrict__ chunk_start, int num_graphs, int rows_per_wg,
+    float* __restrict__ gedge) {
+    extern __shared__ float hist[];
+    const int g = find_item(chunk_start, num_graphs, blockIdx.x);
+    const int n = ns[g];
+    const int chunk = blockIdx.x - chunk_start[g];
+    const float* Gg = G + offsets[g];
+    const int32_t* Ig = idx + offsets[g];
+    const int32_t* par = parent + noff[g];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) hist[k] = 0.0f;
+    __syncthreads();
+    const double inv_n = 1.0 / (double)n;
+    const int r0 = chunk * rows_per_wg, r1 = min(n, r0 + rows_per_wg);
+    const size_t e0 = (size_t)r0 * n, e1 = (size_t)r1 * n;
+    int last = -1;
+    float run = 0.0f;
+    for (size_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const int32_t f = Ig[e];
+        // the diagonal (-1), and anything that is not a flat index of this graph
+        if (f < 0 || (uint32_t)f >= (uint32_t)n * (uint32_t)n) continue;
+        const int s = edge_slot((uint32_t)f, (uint32_t)n, inv_n, par);
+        const float gv = Gg[e];
+        if (s != last) {
+            if (last >= 0) atomicAdd(&hist[last], run);
+            last = s;
+            run = gv;
+        } else {
+            run += gv;
+        }
+    }
+    if (last >= 0) atomicAdd(&hist[last], run);
+    __syncthreads();
+    float* ge = gedge + noff[g];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const float h = hist[k];
+        if (h != 0.0f) atomicAdd(&ge[k], h);
+    }
+}
+
+// dX[c] += g_c (x_c - x_p) / w_cp, dX[p] -= the same, for every non-root c.
+__global__ __launch_bounds__(256) void chain_points_kernel(
+    const float* __restrict__ X, const int64_t* __restrict__ xoff,
+    const float* __restrict__ W, const int64_t* __restrict__ offsets,
+    const int64_t* __restrict__ noff, const int32_t* __restrict__ ns,
+    const int32_t* __restrict__ parent, const float* __restrict__ gedge,
+    const int32_t* __restrict__ vstart, int num_graphs, int d, float* __restrict__ dX) {
+    const int g = find_item(vstart, num_graphs, blockIdx.x);
+    const int n = ns[g];
+    const int c = (blockIdx.x - vstart[g]) * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const int p = parent[noff[g] + c];
+    if (p < 0) return;
+    const float gv = gedge[noff[g] + c];
+    const float w = W[offsets[g] + (size_t)c * n + p];
+    if (gv == 0.0f || !(w > 0.0f)) return;
+    const float f = gv / w;
+    const float* Xg = X + xoff[g];
+    float* dXg = dX + xoff[g];
+    for (int t = 0; t < d; ++t) {
+        const float df = Xg[(size_t)c * d + t] - Xg[(size_t)p * d + t];
+        atomicAdd(&dXg[(size_t)c * d + t], f * df);
+        atomicAdd(&dXg[(size_t)p * d + t], -f * df);
+    }
+}
+
+hipError_t run_pairwise(const float* X, const int64_t* xoff, const int64_t* offsets,
+                        const int32_t* ns, const int32_t* tile_start, int num_graphs,
+                        int total_tiles, int d, float* W, hipStream_t s) {
+    if (d < 1 || d > kMaxD) return hipErrorInvalidValue;
+    if (total_tiles == 0) return hipSuccess;
+    pairwise_kernel<<<total_tiles, kPairThreads, 0, s>>>(X, xoff, offsets, ns, tile_start,
+                                                        num_graphs, d, W);
+    return hipGetLastError();
+}
+
+hipError_t run_edge_grad(const float* G, const int32_t* idx, const int64_t* offsets,
+                         const int64_t* noff, const int32_t* ns, const int32_t* parent,
+                         const int32_t* chunk_start, int num_graphs, int total_chunks,
+                         int rows_per_wg, int max_n, float* gedge, hipStream_t s) {
+    if (total_chunks == 0) return hipSuccess;
+    const size_t lds = sizeof(float) * (size_t)max_n;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)edge_grad_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    edge_grad_kernel<<<total_chunks, 256, lds, s>>>(G, idx, offsets, noff, ns, parent,
+                                                   chunk_start, num_graphs, rows_per_wg, gedge);
+    return hipGetLastError();
+}
+
+hipError_t run_chain(const float* X, const int64_t* xoff, const float* W, const int64_t* offsets,
+                     const int64_t* noff, const int32_t* ns, const int32_t* parent,
+                     const float* gedge, const int32_t* vstart, int num_graphs, int total_vblocks,
+                     int d, float* dX, hipStream_t s) {
+    if (total_vblocks == 0) return hipSuccess;
+    chain_points_kernel<<<total_vblocks, 256, 0, s>>>(X, xoff, W, offsets, noff, ns, parent,
+                                                     gedge, vstart, num_graphs, d, dX);
+    return hipGetLastError();
+}
+
+// Capture-safe clear (a kernel, not a memset node).
+__global__ void zero_kernel(uint32_t* __restrict__ p, size_t words) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+hipError_t run_zero(void* p, size_t bytes, hipStream_t s) {
+    const size_t words = bytes / 4;
+    if (!words) return hipSuccess;
+    const size_t blocks = (words + 255) / 256;
+    zero_kernel<<<(unsigned)(blocks < 8192 ? blocks : 8192), 256, 0, s>>>((uint32_t*)p, words);
+    return hipGetLastError();
+}
+
+__global__ void scale_offsets_kernel(const int64_t* __restrict__ noff, int num_graphs, int d,
+                                     int64_t* __restrict__ xoff) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < num_graphs) xoff[g] = noff[g] * d;
+}
+
+hipError_t run_scale_offsets(const int64_t* noff, int num_graphs, int d, int64_t* xoff,
+                             hipStream_t s) {
+    scale_offsets_kernel<<<(num_graphs + 255) / 256, 256, 0, s>>>(noff, num_graphs, d, xoff);
+    return hipGetLastError();
+}
+
+__global__ void single_table_kernel(int n, int32_t* ns, int64_t* offsets, int64_t* noff,
+                                    int32_t* tile_start, int32_t* gchunk_start, int32_t* vstart) {
+    if (threadIdx.x == 0) {
+        ns[0] = n;
+        offsets[0] = 0;
+        noff[0] = 0;
+        tile_start[0] = 0;
+        gchunk_start[0] = 0;
+        vstart[0] = 0;
+    }
+}
+
+hipError_t run_single_table(int n, int32_t* ns, int64_t* offsets, int64_t* noff,
+                            int32_t* tile_start, int32_t* gchunk_start, int32_t* vstart,
+                            hipStream_t s) {
+    single_table_kernel<<<1, 64, 0, s>>>(n, ns, offsets, noff, tile_start, gchunk_start, vstart);
+    return hipGetLastError();
+}
+
+// dW[min(c,p)*n + max(c,p)] = gedge[c] for each tree edge (c, parent c).
+__global__ void edge_to_w_kernel(const float* __restrict__ gedge, const int32_t* __restrict__ parent,
+                                 int n, float* __restrict__ dW) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const int p = parent[c];
+    if (p < 0) return;
+    const int u = c < p ? c : p, v = c < p ? p : c;
+    dW[(size_t)u * n + v] = gedge[c];
+}
+
+hipError_t run_edge_to_w(const float* gedge, const int32_t* parent, int n, float* dW,
+                         hipStream_t s) {
+    edge_to_w_kernel<<<(n + 255) / 256, 256, 0, s>>>(gedge, parent, n, dW);
+    return hipGetLastError();
+}
+
+int pairwise_tile() { return kTile; }
+int pairwise_max_d() { return kMaxD; }
+
+}  // namespace appd

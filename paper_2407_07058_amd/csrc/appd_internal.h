@@ -7,6 +7,8 @@
 
 namespace appd {
 
+void set_last_error(int code);
+
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Carved single-graph workspace (device pointers).
@@ -22,7 +24,59 @@ struct SingleWs {
 
 size_t single_workspace_bytes(int n);
 SingleWs carve_single(void* ws, int n);
+hipError_t run_tree(const float* W, int n, int mode, const SingleWs& w, hipStream_t s);
+hipError_t run_fill(int n, int mode, float* M, int32_t* idx, const SingleWs& w, hipStream_t s);
 hipError_t run_single(const float* W, int n, int mode, float* M, int32_t* idx,
                       const SingleWs& w, hipStream_t s);
+
+// ---- batched path
+constexpr int kBatchClasses = 4;
+
+struct BatchTree {
+    int32_t* order;
+    uint64_t* ek;
+    int32_t* pos;
+    int32_t* parent;
+};
+
+struct BatchPlan {
+    const int32_t* perm;         // [G] graph ids, n descending (device)
+    const int64_t* noff;         // [G] start of graph g's O(n) arrays (device, by graph id)
+    const int32_t* chunk_start;  // [G] first fill block of perm[i] within its class (device)
+    int class_first[kBatchClasses];
+    int class_count[kBatchClasses];
+    int class_chunks[kBatchClasses];
+};
+
+int batch_class_of(int n);
+int batch_rows_per_chunk();
+hipError_t run_batched(const float* W, const int64_t* offsets, const int32_t* ns,
+                       const BatchPlan& plan, const BatchTree& tree, int mode, float* M,
+                       int32_t* idx, hipStream_t s);
+
+// ---- points / gradients
+hipError_t run_pairwise(const float* X, const int64_t* xoff, const int64_t* offsets,
+                        const int32_t* ns, const int32_t* tile_start, int num_graphs,
+                        int total_tiles, int d, float* W, hipStream_t s);
+hipError_t run_edge_grad(const float* G, const int32_t* idx, const int64_t* offsets,
+                         const int64_t* noff, const int32_t* ns, const int32_t* parent,
+                         const int32_t* chunk_start, int num_graphs, int total_chunks,
+                         int rows_per_wg, int max_n, float* gedge, hipStream_t s);
+hipError_t run_chain(const float* X, const int64_t* xoff, const float* W, const int64_t* offsets,
+                     const int64_t* noff, const int32_t* ns, const int32_t* parent,
+                     const float* gedge, const int32_t* vstart, int num_graphs, int total_vblocks,
+                     int d, float* dX, hipStream_t s);
+hipError_t run_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t run_scale_offsets(const int64_t* noff, int num_graphs, int d, int64_t* xoff,
+                             hipStream_t s);
+hipError_t run_single_table(int n, int32_t* ns, int64_t* offsets, int64_t* noff,
+                            int32_t* tile_start, int32_t* gchunk_start, int32_t* vstart,
+                            hipStream_t s);
+hipError_t run_edge_to_w(const float* gedge, const int32_t* parent, int n, float* dW,
+                         hipStream_t s);
+int pairwise_tile();
+int pairwise_max_d();
+constexpr int kGradRows = 32;
+constexpr int kChainThreads = 256;
 
 }  // namespace appd

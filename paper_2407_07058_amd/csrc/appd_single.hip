@@ -112,25 +112,32 @@ SingleWs carve_single(void* ws, int n) {
 }
 
 template <bool WIDEST>
-static hipError_t run_single_t(const float* W, int n, float* M, int32_t* idx,
-                               const SingleWs& w, hipStream_t s) {
-    PrimOut out{w.order, w.ek, w.pos, w.parent};
-    hipError_t e = launch_prim<WIDEST>(W, n, out, s);
-    if (e != hipSuccess) return e;
+static hipError_t run_fill_t(int n, float* M, int32_t* idx, const SingleWs& w, hipStream_t s) {
     const int nb = fill_blocks(n);
     fill_prep_kernel<kFillCB><<<nb, kFillThreads, 0, s>>>(w.pos, w.ek, n, w.blk_sp, w.blk_slot,
                                                          w.blk_gap);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     dim3 grid(nb, (n + kFillRowsPerWG - 1) / kFillRowsPerWG);
     fill_kernel<kFillCB, WIDEST><<<grid, kFillThreads, 0, s>>>(
         w.pos, w.ek, n, w.blk_sp, w.blk_slot, w.blk_gap, M, idx, kFillRowsPerWG);
     return hipGetLastError();
 }
 
+hipError_t run_tree(const float* W, int n, int mode, const SingleWs& w, hipStream_t s) {
+    PrimOut out{w.order, w.ek, w.pos, w.parent};
+    return mode == 1 ? launch_prim<true>(W, n, out, s) : launch_prim<false>(W, n, out, s);
+}
+
+hipError_t run_fill(int n, int mode, float* M, int32_t* idx, const SingleWs& w, hipStream_t s) {
+    return mode == 1 ? run_fill_t<true>(n, M, idx, w, s) : run_fill_t<false>(n, M, idx, w, s);
+}
+
 hipError_t run_single(const float* W, int n, int mode, float* M, int32_t* idx,
                       const SingleWs& w, hipStream_t s) {
-    return mode == 1 ? run_single_t<true>(W, n, M, idx, w, s)
-                     : run_single_t<false>(W, n, M, idx, w, s);
+    hipError_t e = run_tree(W, n, mode, w, s);
+    if (e != hipSuccess) return e;
+    return run_fill(n, mode, M, idx, w, s);
 }
 
 }  // namespace appd

@@ -79,3 +79,48 @@ def test_forward_rejects_small_or_misaligned_workspace():
     need = L.appd_forward_workspace_bytes(100)
     assert L.appd_forward_ws(p, 100, p, p, p, need - 1, None) == appd.APPD_EINVAL
     assert L.appd_forward_ws(p, 100, p, p, ctypes.c_void_p(260), need, None) == appd.APPD_EINVAL
+
+
+def test_batch_plan_struct_layout_matches_header(tmp_path):
+    """The ctypes mirror of appd_batch_plan has the C layout."""
+    import subprocess
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "appd.h"\n'
+                   'int main(){printf("%zu %zu %zu %zu\\n", sizeof(appd_batch_plan),'
+                   'offsetof(appd_batch_plan, class_first), offsetof(appd_batch_plan, pair_tiles),'
+                   'offsetof(appd_batch_plan, ws_bytes));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    P = appd.BatchPlan
+    assert got == [ctypes.sizeof(P), P.class_first.offset, P.pair_tiles.offset, P.ws_bytes.offset]
+
+
+def test_batch_workspace_and_bad_sizes():
+    import numpy as np
+    L = appd.lib()
+    ns = np.array([16, 1024, 3], np.int32)
+    P = ctypes.c_void_p
+    assert L.appd_batch_workspace_bytes(ns.ctypes.data_as(P), 3) > 0
+    bad = np.array([16, 2049], np.int32)
+    assert L.appd_batch_workspace_bytes(bad.ctypes.data_as(P), 2) == 0
+    zero = np.array([0], np.int32)
+    assert L.appd_batch_workspace_bytes(zero.ctypes.data_as(P), 1) == 0
+    plan = appd.BatchPlan()
+    assert L.appd_batch_prepare(bad.ctypes.data_as(P), 2, P(256), 1 << 30, ctypes.byref(plan),
+                                None) == appd.APPD_EINVAL
+    # a plan that was never prepared is rejected before any launch
+    assert L.appd_forward_batched(P(256), 0, P(256), P(256), None, ctypes.byref(plan), P(256),
+                                  None) == appd.APPD_EINVAL
+
+
+def test_grad_calls_reject_bad_arguments():
+    L = appd.lib()
+    P = ctypes.c_void_p
+    p = P(256)
+    assert L.appd_grad_workspace_bytes(0) == 0
+    assert L.appd_pairwise_euclidean(p, 10, 0, p, p, 1 << 20, None) == appd.APPD_EINVAL
+    assert L.appd_pairwise_euclidean(p, 10, 65, p, p, 1 << 20, None) == appd.APPD_EINVAL
+    assert L.appd_pairwise_euclidean(p, 10, 3, p, p, 1, None) == appd.APPD_EINVAL
+    assert L.appd_backward_points(p, 32769, 3, p, p, p, p, p, p, 1 << 30, None) == appd.APPD_EINVAL
+    assert L.appd_backward_w(p, p, None, 10, p, p, 1 << 20, None) == appd.APPD_EINVAL

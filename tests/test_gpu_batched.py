@@ -1,0 +1,254 @@
+"""GPU parity of the batched forward, the point-to-graph kernel and the backward.
+
+Forward outputs are exact selections, so they are compared bit for bit with the
+CPU oracle.  The point-to-graph kernel follows the same operation order as the
+oracle's float32 routine, so W is compared bit for bit too.  Gradients use float
+atomics on the GPU, so they are compared with a tolerance against the oracle's
+float64 reference gradient taken through the same bottleneck edges."""
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2407_07058_amd as appd
+import workloads
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def pool():
+    return ThreadPoolExecutor(8)
+
+
+def unpack(flat, ns, offsets):
+    return [flat[o:o + n * n].reshape(n, n) for n, o in zip(ns, offsets)]
+
+
+def check_batch(Ws, mode=appd.MINIMAX):
+    flat, offsets, ns = workloads.pack(Ws)
+    b = appd.Batch(ns, DEV)
+    assert (b.offsets == offsets).all()
+    M, idx, parent = b.forward(torch.from_numpy(flat).to(DEV), mode=mode, return_parent=True)
+    torch.cuda.synchronize()
+    Ms = unpack(M.cpu().numpy(), ns, offsets)
+    Is = unpack(idx.cpu().numpy(), ns, offsets)
+    ref = oracle.appd_widest if mode == appd.WIDEST else oracle.appd
+
+    def one(g):
+        Mo, io = ref(Ws[g])
+        return np.array_equal(Ms[g].view(np.uint32), Mo.view(np.uint32)) and np.array_equal(Is[g], io)
+
+    with pool() as ex:
+        okays = list(ex.map(one, range(len(Ws))))
+    bad = [g for g, o in enumerate(okays) if not o]
+    assert not bad, "graphs differing from the oracle: %s (n=%s)" % (bad[:5], [int(ns[g]) for g in bad[:5]])
+    return b, M, idx, parent
+
+
+SIZES = [1, 2, 3, 16, 63, 64, 65, 200, 256, 257, 500, 1024, 1025, 1500, 2047, 2048]
+
+
+def mixed_graphs(seed):
+    rng = np.random.default_rng(seed)
+    Ws = []
+    for k, n in enumerate(SIZES * 2):
+        if k % 3 == 0:
+            Ws.append(workloads.integer_weights(n, 3, seed=seed + k))
+        elif k % 3 == 1:
+            Ws.append(workloads.random_symmetric(n, seed=seed + k))
+        else:
+            Ws.append(workloads.euclid_w(rng.random((n, int(rng.choice([2, 8]))))))
+    order = rng.permutation(len(Ws))
+    return [Ws[i] for i in order]
+
+
+def test_batched_mixed_sizes():
+    say("case batched mixed sizes (32 graphs, n 1..2048)")
+    check_batch(mixed_graphs(1))
+
+
+def test_batched_widest():
+    say("case batched widest")
+    check_batch(mixed_graphs(2)[:20], appd.WIDEST)
+
+
+def test_batched_parent_matches_single():
+    say("case batched parent vs single-graph tree")
+    Ws = mixed_graphs(3)[:12]
+    b, M, idx, parent = check_batch(Ws)
+    par = parent.cpu().numpy()
+    for g, W in enumerate(Ws):
+        n = W.shape[0]
+        _, p, _, _ = oracle.mst_prim(W)
+        assert np.array_equal(par[b.noff[g]:b.noff[g] + n], p)
+
+
+@pytest.mark.timeout(600)
+def test_batched_ragged_full_config():
+    """4096 graphs, n log-uniform in [16, 1024], d in {2, 8}: every graph bit-exact."""
+    say("case ragged batch 4096 graphs: generate")
+    pts = workloads.ragged_points()
+    with pool() as ex:
+        Ws = list(ex.map(workloads.euclid_w, pts))
+    say("case ragged batch 4096 graphs: forward + oracle")
+    check_batch(Ws)
+
+
+def test_batched_graph_capture_replays():
+    """The prepared batched forward launches kernels only, so it can be captured
+    in a HIP graph; every replay must equal the eager result."""
+    say("case batched HIP graph capture")
+    Ws = mixed_graphs(4)
+    flat, offsets, ns = workloads.pack(Ws)
+    b = appd.Batch(ns, DEV)
+    Wd = torch.from_numpy(flat).to(DEV)
+    M0, I0 = b.forward(Wd)
+    torch.cuda.synchronize()
+    M = torch.empty_like(M0)
+    I = torch.empty_like(I0)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.forward(Wd, out=(M, I))  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.forward(Wd, out=(M, I))
+    for rep in range(4):
+        M.fill_(-7.0)
+        I.fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(M, M0) and torch.equal(I, I0), "replay %d differs" % rep
+        _ = (M0 * 2).sum().item()  # eager work between replays
+
+
+@pytest.mark.parametrize("n,d", [(1, 3), (7, 2), (100, 8), (257, 16), (1000, 8), (2100, 5)])
+def test_pairwise_single(n, d):
+    say("case pairwise n=%d d=%d" % (n, d))
+    rng = np.random.default_rng(n + d)
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    W = appd.pairwise_euclidean(torch.from_numpy(X).to(DEV))
+    torch.cuda.synchronize()
+    Wo = oracle.pairwise_euclidean_f32(X)
+    assert np.array_equal(W.cpu().numpy().view(np.uint32), Wo.view(np.uint32))
+
+
+@pytest.mark.parametrize("scale", [1e-21, 1e-3, 1e18])
+def test_pairwise_extreme_scales(scale):
+    """Tiny coordinates push the sums into the subnormal range, huge ones near
+    the top of float32: the square root must still be correctly rounded."""
+    say("case pairwise scale=%g" % scale)
+    rng = np.random.default_rng(11)
+    X = (rng.standard_normal((300, 3)) * scale).astype(np.float32)
+    W = appd.pairwise_euclidean(torch.from_numpy(X).to(DEV))
+    torch.cuda.synchronize()
+    Wo = oracle.pairwise_euclidean_f32(X)
+    assert np.array_equal(W.cpu().numpy().view(np.uint32), Wo.view(np.uint32))
+
+
+def test_pairwise_batched():
+    say("case pairwise batched")
+    rng = np.random.default_rng(5)
+    ns = [1, 5, 64, 65, 300, 1024, 2048, 17]
+    d = 8
+    Xs = [rng.standard_normal((n, d)).astype(np.float32) for n in ns]
+    b = appd.Batch(ns, DEV)
+    W = b.pairwise(torch.from_numpy(np.concatenate(Xs)).to(DEV).contiguous(), d)
+    torch.cuda.synchronize()
+    Ws = unpack(W.cpu().numpy(), ns, b.offsets)
+    for X, Wg in zip(Xs, Ws):
+        assert np.array_equal(Wg.view(np.uint32), oracle.pairwise_euclidean_f32(X).view(np.uint32))
+
+
+def grad_close(got, ref):
+    tol = 1e-4 * np.abs(ref).max() + 1e-4 * np.abs(ref)
+    err = np.abs(got - ref)
+    assert (err <= tol).all(), "max err %g (ref max %g)" % (err.max(), np.abs(ref).max())
+
+
+def ref_grad(X, G):
+    """Oracle float64 gradient through the oracle's own float32 forward."""
+    W32 = oracle.pairwise_euclidean_f32(X)
+    _, idx = oracle.appd(W32)
+    return oracle.grad_points(X.astype(np.float64), G.astype(np.float64), idx), W32, idx
+
+
+@pytest.mark.parametrize("n", [2, 3, 50, 513, 2048])
+def test_backward_points_single(n):
+    say("case backward points n=%d" % n)
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((n, 8)).astype(np.float32)
+    G = rng.standard_normal((n, n)).astype(np.float32)
+    Xd = torch.from_numpy(X).to(DEV).requires_grad_(True)
+    M, idx = appd.appd_points(Xd)
+    (M * torch.from_numpy(G).to(DEV)).sum().backward()
+    torch.cuda.synchronize()
+    ref, W32, io = ref_grad(X, G)
+    assert np.array_equal(idx.cpu().numpy(), io)
+    grad_close(Xd.grad.cpu().numpy().astype(np.float64), ref)
+
+
+def test_backward_w_single():
+    say("case backward W n=700")
+    n = 700
+    W = workloads.integer_weights(n, 5, seed=2) + workloads.random_symmetric(n, seed=3)
+    np.fill_diagonal(W, 0)
+    G = np.random.default_rng(4).standard_normal((n, n)).astype(np.float32)
+    Wd = torch.from_numpy(W).to(DEV).requires_grad_(True)
+    M, idx = appd.APPDWeights.apply(Wd)
+    (M * torch.from_numpy(G).to(DEV)).sum().backward()
+    torch.cuda.synchronize()
+    _, io = oracle.appd(W)
+    ref = np.zeros(n * n)
+    off = io >= 0
+    np.add.at(ref, io[off], G.astype(np.float64)[off])
+    grad_close(Wd.grad.cpu().numpy().ravel().astype(np.float64), ref)
+
+
+@pytest.mark.timeout(600)
+def test_differentiable_batch_full_config():
+    """256 graphs, n uniform in {64..2048}, X ~ N(0, I_8): W bit-exact, M and idx
+    bit-exact, dX against the float64 reference gradient of every graph."""
+    say("case differentiable batch 256 graphs: generate")
+    items = workloads.diff_batch()
+    ns = [x.shape[0] for x, _ in items]
+    d = 8
+    b = appd.Batch(ns, DEV)
+    X = torch.from_numpy(np.concatenate([x for x, _ in items])).to(DEV).requires_grad_(True)
+    Gflat = torch.from_numpy(np.concatenate([g.ravel() for _, g in items])).to(DEV)
+    say("case differentiable batch: forward + backward")
+    M, idx = appd.appd_points_batched(X, b, d)
+    (M * Gflat).sum().backward()
+    torch.cuda.synchronize()
+    Ms = unpack(M.detach().cpu().numpy(), ns, b.offsets)
+    Is = unpack(idx.cpu().numpy(), ns, b.offsets)
+    dX = X.grad.cpu().numpy().astype(np.float64)
+    say("case differentiable batch: oracle")
+
+    def one(g):
+        x, G = items[g]
+        ref, W32, io = ref_grad(x, G)
+        Mo, _ = oracle.appd(W32)
+        o = int(b.noff[g])
+        okf = np.array_equal(Ms[g].view(np.uint32), Mo.view(np.uint32)) and np.array_equal(Is[g], io)
+        got = dX[o:o + x.shape[0]]
+        tol = 1e-4 * np.abs(ref).max() + 1e-4 * np.abs(ref)
+        return okf, bool((np.abs(got - ref) <= tol).all()), float(np.abs(got - ref).max())
+
+    with pool() as ex:
+        res = list(ex.map(one, range(len(items))))
+    assert all(r[0] for r in res), "forward mismatch in graphs %s" % [g for g, r in enumerate(res) if not r[0]][:5]
+    bad = [(g, r[2]) for g, r in enumerate(res) if not r[1]]
+    assert not bad, "gradient outside tolerance: %s" % bad[:5]

@@ -59,6 +59,14 @@ enum appd_mode {
     APPD_WIDEST = 1   /* widest (maximum capacity) path, Section 4.2 */
 };
 
+/* Optional flags or-ed into `mode` of the single-graph calls: how the spanning
+ * tree is found.  The tree is unique under the edge total order, so every choice
+ * returns identical M, idx, order and parent. */
+#define APPD_TREE_AUTO 0x00    /* by size */
+#define APPD_TREE_PRIM 0x10    /* Prim's algorithm in one workgroup (Section 3) */
+#define APPD_TREE_BORUVKA 0x20 /* Boruvka rounds over per-row candidate lists, then
+                                  Prim's attachment order rebuilt from the tree */
+
 const char* appd_error_string(int code);
 int appd_get_last_error(void);
 
@@ -78,7 +86,8 @@ int appd_forward_ws(const float* W, int n, float* M, int32_t* idx, void* ws, siz
 
 /*
  * Extended single-graph forward.
- *   mode      APPD_MINIMAX or APPD_WIDEST.
+ *   mode      APPD_MINIMAX or APPD_WIDEST, optionally or-ed with one
+ *             APPD_TREE_* flag.
  *   order     nullable, n int32: order[k] = k-th vertex attached by Prim's
  *             algorithm started at vertex 0 (the first step of Section 3).
  *   parent    nullable, n int32: the spanning-tree neighbour each vertex was

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_PKG, "libappd.so")
 MINIMAX = 0
 WIDEST = 1
 MAX_N = 46340
+TREE_FLAGS = {"auto": 0x00, "prim": 0x10, "boruvka": 0x20}
 
 APPD_OK = 0
 APPD_EINVAL = -1
@@ -123,15 +124,24 @@ def workspace_bytes(n: int) -> int:
     return int(lib().appd_forward_workspace_bytes(int(n)))
 
 
+def _mode(mode: int, tree: str) -> int:
+    if tree not in TREE_FLAGS:
+        raise ValueError("tree must be one of %s" % sorted(TREE_FLAGS))
+    return int(mode) | TREE_FLAGS[tree]
+
+
 def forward(W: torch.Tensor, mode: int = MINIMAX, return_tree: bool = False, out=None,
-            workspace: torch.Tensor = None):
+            workspace: torch.Tensor = None, tree: str = "auto"):
     """APPD of one graph: (M float32, idx int32[, order int32, parent int32]).
 
     W: n x n float32 on the GPU, symmetric, zero diagonal, no NaN.
     mode: MINIMAX (Eq. 1-2) or WIDEST (Section 4.2).
     out: optional (M, idx) tensors to write into.
+    tree: "auto", "prim" or "boruvka" -- how the spanning tree is found (the
+        results are identical).
     """
     n = _check_square(W)
+    mode = _mode(mode, tree)
     dev = W.device
     if out is None:
         M = torch.empty((n, n), dtype=torch.float32, device=dev)
@@ -153,10 +163,10 @@ def forward(W: torch.Tensor, mode: int = MINIMAX, return_tree: bool = False, out
     return M, idx
 
 
-def tree(W: torch.Tensor, workspace: torch.Tensor, mode: int = MINIMAX):
+def tree(W: torch.Tensor, workspace: torch.Tensor, mode: int = MINIMAX, tree: str = "auto"):
     """Phase 1 only: spanning tree and attachment order into `workspace`."""
     n = _check_square(W)
-    _check(lib().appd_tree(_ptr(W), n, int(mode), None, None, _ptr(workspace),
+    _check(lib().appd_tree(_ptr(W), n, _mode(mode, tree), None, None, _ptr(workspace),
                            workspace.numel(), _stream(W.device)), "appd_tree")
 
 

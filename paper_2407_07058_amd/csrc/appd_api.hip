@@ -46,7 +46,7 @@ size_t appd_forward_workspace_bytes(int n) {
 
 int appd_forward_ex(const float* W, int n, int mode, float* M, int32_t* idx, int32_t* order,
                     int32_t* parent, void* ws, size_t ws_bytes, void* stream) {
-    if (bad_n(n) || !W || !M || !idx || (mode != APPD_MINIMAX && mode != APPD_WIDEST))
+    if (bad_n(n) || !W || !M || !idx || !appd::valid_mode(mode))
         return fail(APPD_EINVAL);
     hipStream_t s = (hipStream_t)stream;
     const size_t need = appd::single_workspace_bytes(n);
@@ -85,7 +85,7 @@ int appd_forward(const float* W, int n, float* M, int32_t* idx, void* stream) {
 
 int appd_tree(const float* W, int n, int mode, int32_t* order, int32_t* parent, void* ws,
               size_t ws_bytes, void* stream) {
-    if (bad_n(n) || !W || !ws || (mode != APPD_MINIMAX && mode != APPD_WIDEST)) return fail(APPD_EINVAL);
+    if (bad_n(n) || !W || !ws || !appd::valid_mode(mode)) return fail(APPD_EINVAL);
     if (ws_bytes < appd::single_workspace_bytes(n) || ((uintptr_t)ws & 255u)) return fail(APPD_EINVAL);
     appd::SingleWs w = appd::carve_single(ws, n);
     if (order) w.order = order;
@@ -99,7 +99,7 @@ int appd_tree(const float* W, int n, int mode, int32_t* order, int32_t* parent, 
 
 int appd_fill(int n, int mode, const void* ws, size_t ws_bytes, float* M, int32_t* idx,
               void* stream) {
-    if (bad_n(n) || !ws || !M || !idx || (mode != APPD_MINIMAX && mode != APPD_WIDEST)) return fail(APPD_EINVAL);
+    if (bad_n(n) || !ws || !M || !idx || !appd::valid_mode(mode)) return fail(APPD_EINVAL);
     if (ws_bytes < appd::single_workspace_bytes(n) || ((uintptr_t)ws & 255u)) return fail(APPD_EINVAL);
     appd::SingleWs w = appd::carve_single(const_cast<void*>(ws), n);
     if (appd::run_fill(n, mode, M, idx, w, (hipStream_t)stream) != hipSuccess) {

@@ -20,7 +20,14 @@ struct SingleWs {
     uint16_t* blk_sp;
     uint16_t* blk_slot;
     uint64_t* blk_gap;
+    void* tree_ws;  // scratch of the parallel tree
 };
+
+size_t tree_workspace_bytes(int n);
+struct PrimOut;
+hipError_t run_tree_parallel(const float* W, int n, int mode, const PrimOut& out, void* tws,
+                             hipStream_t s);
+bool valid_mode(int mode);
 
 size_t single_workspace_bytes(int n);
 SingleWs carve_single(void* ws, int n);

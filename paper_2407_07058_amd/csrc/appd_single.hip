@@ -2,6 +2,7 @@
 #include "appd_fill.h"
 #include "appd_internal.h"
 #include "appd_prim.h"
+#include "appd.h"
 
 namespace appd {
 
@@ -87,6 +88,7 @@ size_t single_workspace_bytes(int n) {
     off = align_up(off + 2 * nb);         // blk_sp
     off = align_up(off + 2 * nb);         // blk_slot
     off = align_up(off + 8 * nb);         // blk_gap
+    off = align_up(off + tree_workspace_bytes(n));
     return off;
 }
 
@@ -108,7 +110,17 @@ SingleWs carve_single(void* ws, int n) {
     w.blk_slot = (uint16_t*)(b + off);
     off = align_up(off + 2 * nb);
     w.blk_gap = (uint64_t*)(b + off);
+    off = align_up(off + 8 * nb);
+    w.tree_ws = b + off;
     return w;
+}
+
+// below this size Prim's sequential chain is short enough
+constexpr int kParallelTreeMinN = 512;
+
+bool valid_mode(int mode) {
+    if (mode & ~0x31) return false;
+    return (mode & 0x30) != 0x30;
 }
 
 template <bool WIDEST>
@@ -126,11 +138,15 @@ static hipError_t run_fill_t(int n, float* M, int32_t* idx, const SingleWs& w, h
 
 hipError_t run_tree(const float* W, int n, int mode, const SingleWs& w, hipStream_t s) {
     PrimOut out{w.order, w.ek, w.pos, w.parent};
-    return mode == 1 ? launch_prim<true>(W, n, out, s) : launch_prim<false>(W, n, out, s);
+    const int algo = mode & 0x30;
+    const bool parallel =
+        algo == APPD_TREE_BORUVKA || (algo == APPD_TREE_AUTO && n >= kParallelTreeMinN);
+    if (parallel) return run_tree_parallel(W, n, mode, out, w.tree_ws, s);
+    return (mode & 1) ? launch_prim<true>(W, n, out, s) : launch_prim<false>(W, n, out, s);
 }
 
 hipError_t run_fill(int n, int mode, float* M, int32_t* idx, const SingleWs& w, hipStream_t s) {
-    return mode == 1 ? run_fill_t<true>(n, M, idx, w, s) : run_fill_t<false>(n, M, idx, w, s);
+    return (mode & 1) ? run_fill_t<true>(n, M, idx, w, s) : run_fill_t<false>(n, M, idx, w, s);
 }
 
 hipError_t run_single(const float* W, int n, int mode, float* M, int32_t* idx,

@@ -1,0 +1,113 @@
+"""GPU parity of the parallel spanning-tree path (Boruvka rounds + Prim order
+rebuilt from the tree) against the CPU oracle, and against the sequential Prim
+kernel: M, idx, the attachment order and the parents must all be identical."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2407_07058_amd as appd
+import workloads
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run(W, tree, mode=appd.MINIMAX):
+    Wd = torch.from_numpy(np.ascontiguousarray(W, np.float32)).to(DEV)
+    out = appd.forward(Wd, mode=mode, return_tree=True, tree=tree)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in out]
+
+
+def check(W, mode=appd.MINIMAX):
+    M, idx, order, parent = run(W, "boruvka", mode)
+    Mo, io = oracle.appd_widest(W) if mode == appd.WIDEST else oracle.appd(W)
+    o, p, _, _ = oracle.mst_prim(W, widest=(mode == appd.WIDEST))
+    assert np.array_equal(order, o), "attachment order differs"
+    assert np.array_equal(parent, p), "parents differ"
+    assert np.array_equal(M.view(np.uint32), Mo.view(np.uint32)) and np.array_equal(idx, io)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 17, 64, 100, 257, 1000, 1025, 3000])
+def test_boruvka_random(n):
+    say("case boruvka random n=%d" % n)
+    check(workloads.random_symmetric(n, seed=n + 1))
+
+
+@pytest.mark.parametrize("n", [2, 9, 300, 2048])
+def test_boruvka_ties(n):
+    say("case boruvka ties n=%d" % n)
+    check(workloads.integer_weights(n, 3, seed=n))
+    check(workloads.integer_weights(n, 2, seed=n + 7) - 1.0)
+
+
+@pytest.mark.parametrize("n", [500, 3000])
+def test_boruvka_points_and_mixture(n):
+    say("case boruvka points/mixture n=%d" % n)
+    check(workloads.euclid_w(workloads.single_points_2d(n, seed=n)))
+    check(workloads.euclid_w(workloads.gaussian_mixture_points(n, seed=n)))
+
+
+def test_boruvka_all_equal():
+    say("case boruvka all-equal")
+    n = 1500
+    W = np.full((n, n), 0.5, np.float32)
+    np.fill_diagonal(W, 0)
+    check(W)
+
+
+@pytest.mark.parametrize("n", [7, 600, 2500])
+def test_boruvka_widest(n):
+    say("case boruvka widest n=%d" % n)
+    check(workloads.random_symmetric(n, seed=3 * n), appd.WIDEST)
+    check(workloads.integer_weights(n, 4, seed=n), appd.WIDEST)
+
+
+def test_boruvka_separated_clusters():
+    """Far-apart tight clusters: every candidate list stays inside its cluster,
+    so the refresh passes (and possibly the sequential fallback) are exercised."""
+    say("case boruvka separated clusters")
+    rng = np.random.default_rng(5)
+    centres = rng.random((40, 3)) * 1000
+    X = centres[rng.integers(0, 40, 2000)] + rng.standard_normal((2000, 3))
+    check(workloads.euclid_w(X))
+    # clusters within clusters within clusters
+    X = np.concatenate([c + s * rng.standard_normal((50, 2))
+                        for c in rng.random((8, 2)) * 1e6 for s in (1.0, 10.0, 100.0)])
+    check(workloads.euclid_w(X))
+
+
+def test_boruvka_equals_prim_mixture_full():
+    say("case boruvka vs prim, mixture n=8192")
+    W = workloads.config_mixture(8192)
+    a = run(W, "boruvka")
+    b = run(W, "prim")
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    Mo, io = oracle.appd(W)
+    assert np.array_equal(a[0].view(np.uint32), Mo.view(np.uint32)) and np.array_equal(a[1], io)
+
+
+@pytest.mark.timeout(400)
+def test_boruvka_uniform_full_sampled():
+    n = 32768
+    say("case boruvka uniform n=32768: generate")
+    W = workloads.config_uniform(n)
+    say("case boruvka uniform n=32768: forward (boruvka, prim)")
+    Wd = torch.from_numpy(W).to(DEV)
+    Ma, Ia, oa, pa = appd.forward(Wd, return_tree=True, tree="boruvka")
+    torch.cuda.synchronize()
+    o, p, _, _ = oracle.mst_prim(W)
+    assert np.array_equal(oa.cpu().numpy(), o) and np.array_equal(pa.cpu().numpy(), p)
+    rows = np.arange(0, n, 997)
+    Mo, io = oracle.appd_rows(W, rows)
+    assert np.array_equal(Ma[rows].cpu().numpy().view(np.uint32), Mo.view(np.uint32))
+    assert np.array_equal(Ia[rows].cpu().numpy(), io)

@@ -40,6 +40,8 @@ constexpr int kPassThreads = 256;  // 4 waves, one row each
 constexpr int kRoundThreads = 1024;
 constexpr int kRankTile = 256;
 constexpr int kMaxLdsN = 32768;    // comp + parent as 16-bit values in LDS
+constexpr int kLdsBytes = 150 * 1024;  // dynamic LDS the rounds kernel may take
+constexpr int kTableBytes = 28;        // per-component table entry
 constexpr uint64_t kNone = ~0ull;
 
 // control block (int32 words); word 32 holds the number of rank tiles
@@ -75,8 +77,11 @@ __global__ void tree_init_kernel(int n, int32_t* comp, uint64_t* best, uint64_t*
 }
 
 // ---------------------------------------------------------------- pass
-// One wave per row: each lane keeps its K smallest entries in registers
-// (insertion), then K rounds of wave-minimum extraction merge the 64 lists.
+// One wave per row.  Lanes 0..K-1 hold the row's K smallest entries seen so
+// far, in ascending order; tau is the K-th.  An element is offered only when it
+// beats tau, so after the first few columns almost every element costs one
+// compare: a candidate is broadcast, its rank among the list (a ballot) gives
+// its slot, the lanes above shift up by one.
 // VEC: rows are 16-byte aligned (n % 4 == 0), each lane reads 4 columns at once.
 template <bool WIDEST, bool FILTER, bool VEC>
 __global__ __launch_bounds__(kPassThreads) void tree_pass_kernel(const float* __restrict__ W,
@@ -91,27 +96,30 @@ __global__ __launch_bounds__(kPassThreads) void tree_pass_kernel(const float* __
     if (u >= n) return;  // no barrier in this kernel
     const float* row = W + (size_t)u * (size_t)n;
     const int cu = FILTER ? comp[u] : u;
-    uint64_t top[kK];
-#pragma unroll
-    for (int q = 0; q < kK; ++q) top[q] = kNone;
-    auto consider = [&](float w, int v, int cv) {
+    uint64_t mine = kNone;  // this lane's slot of the sorted list (lanes < K)
+    uint64_t tau = kNone;   // the K-th smallest so far (wave-uniform)
+    auto offer = [&](float w, int v, int cv) {
         const bool skip = FILTER ? (cv == cu) : (v == u);
         const uint64_t e =
             skip ? kNone : (((uint64_t)ord32(WIDEST ? -w : w) << 32) | (uint32_t)v);
-        if (e < top[kK - 1]) {
-            uint64_t x = e;
-#pragma unroll
-            for (int q = 0; q < kK; ++q) {  // insert, keeping top[] ascending
-                const uint64_t t = top[q];
-                const bool sw = x < t;
-                top[q] = sw ? x : t;
-                x = sw ? t : x;
+        uint64_t bal = __ballot(e < tau);
+        while (bal) {
+            const int src = __ffsll((unsigned long long)bal) - 1;
+            bal &= bal - 1;
+            const uint64_t x = shfl_u64(e, src);
+            if (x < tau) {
+                const int pos = __popcll(__ballot(lane < kK && mine < x));
+                const uint64_t below = shfl_up_u64(mine, 1);
+                if (lane < kK) mine = lane > pos ? below : (lane == pos ? x : mine);
+                tau = shfl_u64(mine, kK - 1);
             }
         }
     };
     if (VEC) {
         constexpr int U = 4;
-        for (int base = lane * 4; base < n; base += kWave * 4 * U) {
+        // the trip count must be the same for every lane (offer() is wave-wide)
+        for (int b0 = 0; b0 < n; b0 += kWave * 4 * U) {
+            const int base = b0 + lane * 4;
             float4 x[U];
             int4 c[U];
 #pragma unroll
@@ -120,49 +128,42 @@ __global__ __launch_bounds__(kPassThreads) void tree_pass_kernel(const float* __
                 if (v < n) {
                     x[j] = *(const float4*)(row + v);
                     if (FILTER) c[j] = *(const int4*)(comp + v);
+                } else {
+                    x[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    c[j] = make_int4(cu, cu, cu, cu);
                 }
             }
 #pragma unroll
             for (int j = 0; j < U; ++j) {
                 const int v = base + j * kWave * 4;
-                if (v < n) {
-                    consider(x[j].x, v, FILTER ? c[j].x : 0);
-                    consider(x[j].y, v + 1, FILTER ? c[j].y : 0);
-                    consider(x[j].z, v + 2, FILTER ? c[j].z : 0);
-                    consider(x[j].w, v + 3, FILTER ? c[j].w : 0);
-                }
+                // out-of-range columns (v >= n) are offered as skipped entries
+                const bool in = v < n;
+                offer(x[j].x, in ? v : u, FILTER ? c[j].x : 0);
+                offer(x[j].y, in ? v + 1 : u, FILTER ? c[j].y : 0);
+                offer(x[j].z, in ? v + 2 : u, FILTER ? c[j].z : 0);
+                offer(x[j].w, in ? v + 3 : u, FILTER ? c[j].w : 0);
             }
         }
     } else {
         constexpr int U = 8;
-        for (int base = lane; base < n; base += kWave * U) {
+        for (int b0 = 0; b0 < n; b0 += kWave * U) {
+            const int base = b0 + lane;
             float x[U];
             int c[U];
 #pragma unroll
             for (int j = 0; j < U; ++j) {
                 const int v = base + j * kWave;
-                if (v < n) {
-                    x[j] = row[v];
-                    if (FILTER) c[j] = comp[v];
-                }
+                x[j] = v < n ? row[v] : 0.0f;
+                c[j] = (FILTER && v < n) ? comp[v] : cu;
             }
 #pragma unroll
             for (int j = 0; j < U; ++j) {
                 const int v = base + j * kWave;
-                if (v < n) consider(x[j], v, FILTER ? c[j] : 0);
+                offer(x[j], v < n ? v : u, FILTER ? c[j] : 0);
             }
         }
     }
-    uint64_t* out = lists + (size_t)u * kK;
-    for (int q = 0; q < kK; ++q) {
-        const uint64_t m = wave_min_u64(top[0]);
-        if (lane == 0) out[q] = m;
-        if (m != kNone && top[0] == m) {  // entries are unique: exactly one lane pops
-#pragma unroll
-            for (int z = 0; z < kK - 1; ++z) top[z] = top[z + 1];
-            top[kK - 1] = kNone;
-        }
-    }
+    if (lane < kK) lists[(size_t)u * kK + lane] = mine;
     if (lane == 0) lptr[u] = 0;
 }
 
@@ -180,16 +181,7 @@ struct RoundArgs {
     int32_t* hy;  // endpoint outside
     int32_t* par;
     int32_t* ctrl;
-    // order phase (run once, by the call that completes the tree)
-    uint64_t* keyup;
-    int32_t* link;
-    int32_t* size;
-    int32_t* gcount;
-    int32_t* gstart;
-    int32_t* gfill;
-    int32_t* tstart;
-    int32_t* grouped;
-    int32_t* rank;
+    int cm;  // capacity of the per-component LDS tables
 };
 
 // Block-wide exclusive scan (one workgroup of kRoundThreads threads).
@@ -208,34 +200,75 @@ __device__ __forceinline__ int block_excl_scan(int x, int* s) {
     return r;
 }
 
-// One workgroup.  With LDS: component labels and parents as 16-bit values in
-// LDS (n <= kMaxLdsN); otherwise the global arrays are used directly.
+// One workgroup.  Components are numbered densely 0..C-1 and renumbered after
+// every round.  Per vertex: component and parent, as 16-bit values in LDS when
+// n <= kMaxLdsN (else the global arrays).  Per component: best candidate, lower
+// bound, hook target and hooking edge -- in LDS tables once C <= cm (so that
+// the many vertices of a large component meet in LDS atomics, not at one L2
+// address), in the global arrays before that.
 template <bool LDS, bool WIDEST>
 __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a) {
-    extern __shared__ uint16_t s_mem[];  // [0,n): component, [n,2n): parent
+    extern __shared__ uint64_t s_dyn[];
     __shared__ int s_flag[4];
     __shared__ int s_scan[kRoundThreads];
     const int n = a.n;
+    const int cm = a.cm;
     const int t = threadIdx.x;
     const int lane = t & (kWave - 1);
     int32_t* ctrl = a.ctrl;
     if (ctrl[C_ORDERED] || ctrl[C_FALLBACK]) return;
+    // LDS layout: [per-component tables: best, lb (u64) | hook, hx, hy (i32)]
+    //             [per-vertex: component, parent (u16)]
+    uint64_t* t_best = s_dyn;
+    uint64_t* t_lb = t_best + cm;
+    int32_t* t_hook = (int32_t*)(t_lb + cm);
+    int32_t* t_hx = t_hook + cm;
+    int32_t* t_hy = t_hx + cm;
+    uint16_t* v_comp = (uint16_t*)(t_hy + cm);
+    uint16_t* v_par = v_comp + n;
     constexpr uint16_t NIL = 0xffff;
-    auto getc = [&](int v) -> int { return LDS ? (int)s_mem[v] : a.comp[v]; };
+    auto getc = [&](int v) -> int { return LDS ? (int)v_comp[v] : a.comp[v]; };
     auto setc = [&](int v, int c) {
-        if (LDS) s_mem[v] = (uint16_t)c;
+        if (LDS) v_comp[v] = (uint16_t)c;
         else a.comp[v] = c;
     };
     auto getp = [&](int v) -> int {
         if (LDS) {
-            const uint16_t x = s_mem[n + v];
+            const uint16_t x = v_par[v];
             return x == NIL ? -1 : (int)x;
         }
         return a.par[v];
     };
     auto setp = [&](int v, int p) {
-        if (LDS) s_mem[n + v] = p < 0 ? NIL : (uint16_t)p;
+        if (LDS) v_par[v] = p < 0 ? NIL : (uint16_t)p;
         else a.par[v] = p;
+    };
+    int C = ctrl[C_NCOMP];
+    bool small = C <= cm;
+    auto get_best = [&](int d) { return small ? t_best[d] : ld_l2(&a.best[d]); };
+    auto get_lb = [&](int d) { return small ? t_lb[d] : ld_l2(&a.lb[d]); };
+    auto min_best = [&](int d, uint64_t k) {
+        if (small) atomicMin((unsigned long long*)&t_best[d], (unsigned long long)k);
+        else atomicMin((unsigned long long*)&a.best[d], (unsigned long long)k);
+    };
+    auto min_lb = [&](int d, uint64_t k) {
+        if (small) atomicMin((unsigned long long*)&t_lb[d], (unsigned long long)k);
+        else atomicMin((unsigned long long*)&a.lb[d], (unsigned long long)k);
+    };
+    auto geth = [&](int d) { return small ? t_hook[d] : a.hook[d]; };
+    auto seth = [&](int d, int h) {
+        if (small) t_hook[d] = h;
+        else a.hook[d] = h;
+    };
+    auto gethx = [&](int d) { return small ? t_hx[d] : a.hx[d]; };
+    auto sethx = [&](int d, int x) {
+        if (small) t_hx[d] = x;
+        else a.hx[d] = x;
+    };
+    auto gethy = [&](int d) { return small ? t_hy[d] : a.hy[d]; };
+    auto sethy = [&](int d, int y) {
+        if (small) t_hy[d] = y;
+        else a.hy[d] = y;
     };
     // the rooted forest built so far (first call: every vertex its own root)
     const bool first = ctrl[C_ROUNDS] == 0;
@@ -247,67 +280,91 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
             a.par[v] = -1;
         }
     }
+    if (small)
+        for (int d = t; d < C; d += kRoundThreads) t_best[d] = t_lb[d] = kNone;
     __syncthreads();
 
+    constexpr int kChunk = 8;
+    constexpr int kStride = kChunk * kRoundThreads;
     for (int guard = 0; guard < 64 && !ctrl[C_DONE]; ++guard) {
         if (t == 0) {
             s_flag[0] = 0;  // components that decided this round
-            s_flag[2] = 0;  // components left
             ctrl[C_ROUNDS] += 1;
         }
         // 1. cheapest outgoing candidate (or lower bound) of every vertex; a wave
         //    whose vertices share one component sends one atomic per minimum.
-        for (int base = 0; base < n; base += kRoundThreads) {
-            const int u = base + t;
-            const bool act = u < n;
-            int cu = -1;
-            uint64_t kc = kNone, kb = kNone;
-            if (act) {
-                cu = getc(u);
-                int p = a.lptr[u];
-                const uint64_t* L = a.lists + (size_t)u * kK;
-                uint64_t ent = p < kK ? L[p] : kNone;
-                while (p < kK && ent != kNone && getc((int)(uint32_t)ent) == cu) {
-                    ++p;
-                    ent = p < kK ? L[p] : kNone;
-                }
-                if (p < kK && ent == kNone) p = kK;  // short list: no vertex beyond it
-                a.lptr[u] = p;
-                if (p < kK) {
-                    kc = edge_key_of(ent, u, n);
-                } else {
-                    const uint64_t last = L[kK - 1];
-                    if (last != kNone) kb = edge_key_of(last, u, n);
-                }
+        //    The list words a vertex usually needs (its current entry, the next
+        //    one and the last) are gathered for kChunk vertices before use.
+        for (int base = 0; base < n; base += kStride) {
+            int pp[kChunk];
+            uint64_t e0[kChunk], e1[kChunk], el[kChunk];
+#pragma unroll
+            for (int i = 0; i < kChunk; ++i) {
+                const int u = base + i * kRoundThreads + t;
+                pp[i] = u < n ? a.lptr[u] : kK;
             }
-            const int c0 = __shfl(cu, 0);
-            const uint64_t same = __ballot(act && cu == c0);
-            const uint64_t acts = __ballot(act);
-            if (same == acts) {
-                const uint64_t mc = wave_min_u64(kc), mb = wave_min_u64(kb);
-                if (lane == 0) {
-                    if (mc != kNone) atomicMin((unsigned long long*)&a.best[c0], mc);
-                    if (mb != kNone) atomicMin((unsigned long long*)&a.lb[c0], mb);
+#pragma unroll
+            for (int i = 0; i < kChunk; ++i) {
+                const int u = base + i * kRoundThreads + t;
+                const uint64_t* L = a.lists + (size_t)u * kK;
+                const bool ok = u < n && pp[i] < kK;
+                e0[i] = ok ? L[pp[i]] : kNone;
+                e1[i] = (ok && pp[i] + 1 < kK) ? L[pp[i] + 1] : kNone;
+                el[i] = u < n ? L[kK - 1] : kNone;
+            }
+#pragma unroll
+            for (int i = 0; i < kChunk; ++i) {
+                const int u = base + i * kRoundThreads + t;
+                const bool act = u < n;
+                int cu = -1;
+                uint64_t kc = kNone, kb = kNone;
+                if (act) {
+                    const uint64_t* L = a.lists + (size_t)u * kK;
+                    cu = getc(u);
+                    int p = pp[i];
+                    uint64_t ent = e0[i];
+                    if (p < kK && ent != kNone && getc((int)(uint32_t)ent) == cu) {
+                        ++p;
+                        ent = e1[i];
+                        while (p < kK && ent != kNone && getc((int)(uint32_t)ent) == cu) {
+                            ++p;
+                            ent = p < kK ? L[p] : kNone;
+                        }
+                    }
+                    if (p < kK && ent == kNone) p = kK;  // short list: nothing beyond it
+                    if (p != pp[i]) a.lptr[u] = p;
+                    if (p < kK) kc = edge_key_of(ent, u, n);
+                    else if (el[i] != kNone) kb = edge_key_of(el[i], u, n);
                 }
-            } else if (act) {
-                if (kc != kNone) atomicMin((unsigned long long*)&a.best[cu], kc);
-                if (kb != kNone) atomicMin((unsigned long long*)&a.lb[cu], kb);
+                const int c0 = __shfl(cu, 0);
+                const uint64_t same = __ballot(act && cu == c0);
+                const uint64_t acts = __ballot(act);
+                if (same == acts) {
+                    const uint64_t mc = wave_min_u64(kc), mb = wave_min_u64(kb);
+                    if (lane == 0) {
+                        if (mc != kNone) min_best(c0, mc);
+                        if (mb != kNone) min_lb(c0, mb);
+                    }
+                } else if (act) {
+                    if (kc != kNone) min_best(cu, kc);
+                    if (kb != kNone) min_lb(cu, kb);
+                }
             }
         }
         __syncthreads();
         // 2. decide: a component hooks when its best exact candidate beats every bound
-        for (int c = t; c < n; c += kRoundThreads) {
-            if (getc(c) != c) continue;
-            const uint64_t b = ld_l2(&a.best[c]);
-            a.hook[c] = c;
-            if (b != kNone && b < ld_l2(&a.lb[c])) {
+        for (int d = t; d < C; d += kRoundThreads) {
+            const uint64_t b = get_best(d);
+            const uint64_t l = get_lb(d);
+            seth(d, d);
+            if (b != kNone && b < l) {
                 const uint32_t f = (uint32_t)b;
                 const int x0 = (int)(f / (uint32_t)n), y0 = (int)(f % (uint32_t)n);
-                const bool xin = getc(x0) == c;
+                const bool xin = getc(x0) == d;
                 const int x = xin ? x0 : y0, y = xin ? y0 : x0;
-                a.hx[c] = x;
-                a.hy[c] = y;
-                a.hook[c] = getc(y);
+                sethx(d, x);
+                sethy(d, y);
+                seth(d, getc(y));
                 atomicAdd(&s_flag[0], 1);
             }
         }
@@ -316,25 +373,23 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
         if (decided == 0) {
             // the minima gathered from these lists are stale once the lists are
             // refreshed: clear them for the next call
-            for (int c = t; c < n; c += kRoundThreads) {
-                a.best[c] = kNone;
-                a.lb[c] = kNone;
-            }
+            if (!small)
+                for (int d = t; d < C; d += kRoundThreads) a.best[d] = a.lb[d] = kNone;
             if (t == 0) ctrl[C_NEED_PASS] = 1;
             break;
         }
-        // 3. a mutual pair chose the same edge: the smaller id stays the root.
+        // 3. a mutual pair chose the same edge: the smaller id stays the root
+        //    (points to itself; its partner then sees no mutual pair and hooks).
         //    Every other hooking component re-roots itself at its endpoint,
         //    whose parent becomes the endpoint outside.
-        for (int c = t; c < n; c += kRoundThreads) {
-            if (getc(c) != c) continue;
-            const int h = a.hook[c];
-            if (h == c) continue;
-            if (a.hook[h] == c && ld_l2(&a.best[h]) == ld_l2(&a.best[c]) && c < h) {
-                a.hook[c] = -1 - c;  // root of the pair, restored below
+        for (int d = t; d < C; d += kRoundThreads) {
+            const int h = geth(d);
+            if (h == d) continue;
+            if (d < h && geth(h) == d && get_best(h) == get_best(d)) {
+                seth(d, d);
                 continue;
             }
-            int cur = a.hx[c], prev = a.hy[c];
+            int cur = gethx(d), prev = gethy(d);
             while (cur >= 0) {  // reverse the parent pointers on hx -> old root
                 const int nxt = getp(cur);
                 setp(cur, prev);
@@ -343,19 +398,15 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
             }
         }
         __syncthreads();
-        for (int c = t; c < n; c += kRoundThreads)
-            if (getc(c) == c && a.hook[c] < 0) a.hook[c] = c;
-        __syncthreads();
-        // 4. pointer jumping: every component id -> the root it now belongs to
+        // 4. pointer jumping: every component -> the root it now belongs to
         for (int it = 0; it < 64; ++it) {
             if (t == 0) s_flag[1] = 0;
             __syncthreads();
-            for (int c = t; c < n; c += kRoundThreads) {
-                if (getc(c) != c) continue;
-                const int h = a.hook[c];
-                const int hh = a.hook[h];
+            for (int d = t; d < C; d += kRoundThreads) {
+                const int h = geth(d);
+                const int hh = geth(h);
                 if (hh != h) {
-                    a.hook[c] = hh;
+                    seth(d, hh);
                     s_flag[1] = 1;
                 }
             }
@@ -364,22 +415,32 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
             __syncthreads();  // every thread has read the flag before it is reset
             if (!again) break;
         }
-        // 5. relabel; reset the per-component minima; count the roots
-        for (int u = t; u < n; u += kRoundThreads) setc(u, a.hook[getc(u)]);
+        // 5. number the roots densely (hx of a root now holds its new number)
+        const int per = (C + kRoundThreads - 1) / kRoundThreads;
+        const int d0 = min(C, t * per), d1 = min(C, d0 + per);
+        int cnt = 0;
+        for (int d = d0; d < d1; ++d) cnt += geth(d) == d ? 1 : 0;
+        int id = block_excl_scan(cnt, s_scan);
+        for (int d = d0; d < d1; ++d)
+            if (geth(d) == d) sethx(d, id++);
+        if (t == kRoundThreads - 1) s_flag[2] = id;
         __syncthreads();
-        for (int c = t; c < n; c += kRoundThreads) {
-            a.best[c] = kNone;
-            a.lb[c] = kNone;
-            if (getc(c) == c) atomicAdd(&s_flag[2], 1);
+        const int Cn = s_flag[2];
+        // 6. relabel every vertex; clear the tables for the next round
+        for (int u = t; u < n; u += kRoundThreads) setc(u, gethx(geth(getc(u))));
+        __syncthreads();
+        C = Cn;
+        small = C <= cm;
+        for (int d = t; d < C; d += kRoundThreads) {
+            if (small) t_best[d] = t_lb[d] = kNone;
+            else a.best[d] = a.lb[d] = kNone;
         }
-        __syncthreads();
-        const int left = s_flag[2];
         if (t == 0) {
-            ctrl[C_NCOMP] = left;
-            if (left == 1) ctrl[C_DONE] = 1;
+            ctrl[C_NCOMP] = C;
+            if (C == 1) ctrl[C_DONE] = 1;
         }
         __syncthreads();
-        if (left == 1) break;
+        if (C == 1) break;
     }
     __syncthreads();
     const bool done = ctrl[C_DONE] != 0;
@@ -400,50 +461,74 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
         }
     }
     if (!done) return;
+    if (t == 0) ctrl[C_ORDERED] = 1;  // tree complete and rooted at 0
+}
 
-    // ---- order phase, part 1 (this workgroup): edge keys, links, sizes, groups
-    const float sg = WIDEST ? -1.0f : 1.0f;
-    for (int v = t; v < n; v += kRoundThreads) {
-        const int p = getp(v);
-        uint64_t k = 0;
-        if (p >= 0) k = make_key(sg * a.W[(size_t)v * n + p], flat_idx(v, p, n));
-        a.keyup[v] = k;
-        a.link[v] = p;
-        a.size[v] = 1;
-        a.gcount[v] = 0;
+// ---------------------------------------------------------------- order
+// Every kernel below returns at once unless the rounds completed the tree
+// (else the sequential fallback produced the outputs).  One thread per vertex
+// wherever the work is independent, so each dependent chain is paid once.
+
+// Edge key to the parent, link initialised to the parent.
+template <bool WIDEST>
+__global__ __launch_bounds__(256) void tree_keyup_kernel(const float* __restrict__ W, int n,
+                                                        const int32_t* par, uint64_t* keyup,
+                                                        int32_t* link, int32_t* size,
+                                                        int32_t* gcount, const int32_t* ctrl) {
+    if (!ctrl[C_ORDERED]) return;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int p = par[v];
+    uint64_t k = 0;
+    if (p >= 0) k = make_key((WIDEST ? -1.0f : 1.0f) * W[(size_t)v * n + p], flat_idx(v, p, n));
+    keyup[v] = k;
+    link[v] = p;
+    size[v] = 1;
+    gcount[v] = 0;
+}
+
+// link(v): jump over ancestors whose edge is smaller than e(v).  Any value a
+// link[] entry holds at any time is an ancestor reached over smaller edges
+// only, so a thread may follow entries other threads are still updating, and
+// it publishes its own progress as it goes.  Every jump moves up the tree, so
+// each thread ends.
+__global__ __launch_bounds__(256) void tree_link_kernel(int n, const uint64_t* keyup,
+                                                       int32_t* link, const int32_t* ctrl) {
+    if (!ctrl[C_ORDERED]) return;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v == 0 || v >= n) return;
+    const uint64_t kv = keyup[v];
+    int c = link[v];
+    while (c > 0 && keyup[c] < kv) {
+        c = link[c];
+        link[v] = c;
     }
-    __syncthreads();
-    // link(v): jump over ancestors whose edge is smaller than e(v).  Every link[]
-    // entry is at all times an ancestor reached over smaller edges only, so the
-    // jumps may read entries other threads are updating.
-    for (int it = 0; it < 4096; ++it) {
-        if (t == 0) s_flag[1] = 0;
-        __syncthreads();
-        for (int v = t + 1; v < n; v += kRoundThreads) {
-            const int c = a.link[v];
-            if (c > 0 && a.keyup[c] < a.keyup[v]) {
-                a.link[v] = a.link[c];
-                s_flag[1] = 1;
-            }
-        }
-        __syncthreads();
-        const int again = s_flag[1];
-        __syncthreads();
-        if (!again) break;
-    }
-    // link-subtree sizes and sibling-group sizes
-    for (int v = t + 1; v < n; v += kRoundThreads) {
-        const int g = a.link[v];
-        atomicAdd(&a.gcount[g], 1);
-        for (int x = g; x > 0; x = a.link[x]) atomicAdd(&a.size[x], 1);
-    }
-    __syncthreads();
-    // group starts and rank-tile starts (exclusive scans over n)
+}
+
+// link-subtree sizes and sibling-group sizes
+__global__ __launch_bounds__(256) void tree_sizes_kernel(int n, const int32_t* link,
+                                                        int32_t* size, int32_t* gcount,
+                                                        const int32_t* ctrl) {
+    if (!ctrl[C_ORDERED]) return;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v == 0 || v >= n) return;
+    const int g = link[v];
+    atomicAdd(&gcount[g], 1);
+    for (int x = g; x > 0; x = link[x]) atomicAdd(&size[x], 1);
+}
+
+// One workgroup: group starts and rank-tile starts (exclusive scans over n).
+__global__ __launch_bounds__(kRoundThreads) void tree_scan_kernel(int n, const int32_t* gcount,
+                                                                 int32_t* gstart, int32_t* gfill,
+                                                                 int32_t* tstart, int32_t* ctrl) {
+    __shared__ int s_scan[kRoundThreads];
+    if (!ctrl[C_ORDERED]) return;
+    const int t = threadIdx.x;
     const int per = (n + kRoundThreads - 1) / kRoundThreads;
     const int b0 = min(n, t * per), b1 = min(n, b0 + per);
     int s = 0, ts = 0;
     for (int i = b0; i < b1; ++i) {
-        const int m = ld_l2(&a.gcount[i]);
+        const int m = gcount[i];
         const int nt = (m + kRankTile - 1) / kRankTile;
         s += m;
         ts += m > 1 ? nt * nt : 0;
@@ -451,25 +536,29 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
     int run = block_excl_scan(s, s_scan);
     int trun = block_excl_scan(ts, s_scan);
     for (int i = b0; i < b1; ++i) {
-        const int m = ld_l2(&a.gcount[i]);
+        const int m = gcount[i];
         const int nt = (m + kRankTile - 1) / kRankTile;
-        a.gstart[i] = run;
-        a.gfill[i] = 0;
-        a.tstart[i] = trun;
+        gstart[i] = run;
+        gfill[i] = 0;
+        tstart[i] = trun;
         run += m;
         trun += m > 1 ? nt * nt : 0;
     }
     if (t == kRoundThreads - 1) ctrl[C_TILES] = trun;
-    __syncthreads();
-    for (int v = t + 1; v < n; v += kRoundThreads) {
-        const int g = a.link[v];
-        a.grouped[a.gstart[g] + atomicAdd(&a.gfill[g], 1)] = v;
-        a.rank[v] = 0;
-    }
-    if (t == 0) ctrl[C_ORDERED] = 1;
 }
 
-// ---------------------------------------------------------------- order, part 2
+__global__ __launch_bounds__(256) void tree_group_kernel(int n, const int32_t* link,
+                                                        const int32_t* gstart, int32_t* gfill,
+                                                        int32_t* grouped, int32_t* rank,
+                                                        const int32_t* ctrl) {
+    if (!ctrl[C_ORDERED]) return;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v == 0 || v >= n) return;
+    const int g = link[v];
+    grouped[gstart[g] + atomicAdd(&gfill[g], 1)] = v;
+    rank[v] = 0;
+}
+
 // Rank among siblings: tile (group, v-block, member-block) counts the members
 // of the member block with a smaller key than each v of the v block.
 __global__ __launch_bounds__(kRankTile) void tree_rank_kernel(int n, const int32_t* gcount,
@@ -511,21 +600,30 @@ __global__ __launch_bounds__(kRankTile) void tree_rank_kernel(int n, const int32
     }
 }
 
-// One workgroup: place each vertex's link-subtree size at (group start + rank),
-// then a segmented exclusive scan gives the sizes of smaller siblings.
-__global__ __launch_bounds__(kRoundThreads) void tree_presize_kernel(
-    int n, const int32_t* link, const int32_t* gstart, const int32_t* rank, const int32_t* size,
-    int32_t* sorted_size, int32_t* sorted_grp, int32_t* sorted_pre, const int32_t* ctrl) {
+// Each vertex's link-subtree size at (group start + rank): siblings in key order.
+__global__ __launch_bounds__(256) void tree_place_kernel(int n, const int32_t* link,
+                                                        const int32_t* gstart,
+                                                        const int32_t* rank, const int32_t* size,
+                                                        int32_t* sorted_size, int32_t* sorted_grp,
+                                                        const int32_t* ctrl) {
+    if (!ctrl[C_ORDERED]) return;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v == 0 || v >= n) return;
+    const int g = link[v];
+    const int slot = gstart[g] + rank[v];
+    sorted_size[slot] = size[v];
+    sorted_grp[slot] = g;
+}
+
+// One workgroup: segmented exclusive scan of the placed sizes (segments =
+// sibling groups) -> total size of the smaller siblings of each slot.
+__global__ __launch_bounds__(kRoundThreads) void tree_segscan_kernel(
+    int n, const int32_t* sorted_size, const int32_t* sorted_grp, int32_t* sorted_pre,
+    const int32_t* ctrl) {
     __shared__ int s_val[kRoundThreads];
     __shared__ int s_head[kRoundThreads];
     if (!ctrl[C_ORDERED]) return;
     const int t = threadIdx.x;
-    for (int v = t + 1; v < n; v += kRoundThreads) {
-        const int slot = gstart[link[v]] + rank[v];
-        sorted_size[slot] = size[v];
-        sorted_grp[slot] = link[v];
-    }
-    __syncthreads();
     const int m = n - 1;  // slots
     const int per = (m + kRoundThreads - 1) / kRoundThreads;
     const int b = min(m, t * per), e = min(m, b + per);
@@ -683,15 +781,18 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
     tree_init_kernel<<<max(nb, 1), 256, 0, s>>>(n, w.comp, w.best, w.lb, w.ctrl);
     APPD_CHK();
     const bool lds = n <= kMaxLdsN;
-    const size_t round_lds = lds ? 4 * (size_t)n : 0;
+    const size_t vbytes = lds ? 4 * (size_t)n : 0;
+    int cm = (int)((kLdsBytes - vbytes) / kTableBytes);
+    cm = min(4096, cm) & ~63;
+    const size_t round_lds = (size_t)cm * kTableBytes + vbytes;
     if (round_lds > 64 * 1024) {
-        e = hipFuncSetAttribute((const void*)tree_rounds_kernel<true, WIDEST>,
+        e = hipFuncSetAttribute(lds ? (const void*)tree_rounds_kernel<true, WIDEST>
+                                    : (const void*)tree_rounds_kernel<false, WIDEST>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)round_lds);
         if (e != hipSuccess) return e;
     }
-    RoundArgs ra{W,      n,        w.comp,   w.best,  w.lb,     w.lptr,    w.lists,
-                 w.hook, w.hx,     w.hy,     w.par,   w.ctrl,   w.keyup,   w.link,
-                 w.size, w.gcount, w.gstart, w.gfill, w.tstart, w.grouped, w.rank};
+    RoundArgs ra{W,      n,    w.comp, w.best, w.lb, w.lptr, w.lists,
+                 w.hook, w.hx, w.hy,   w.par,  w.ctrl, cm};
     for (int p = 0; p < kPasses; ++p) {
         if (p == 0) launch_pass<WIDEST, false>(W, n, w, s);
         else launch_pass<WIDEST, true>(W, n, w, s);
@@ -699,17 +800,32 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
         if (lds)
             tree_rounds_kernel<true, WIDEST><<<1, kRoundThreads, round_lds, s>>>(ra);
         else
-            tree_rounds_kernel<false, WIDEST><<<1, kRoundThreads, 0, s>>>(ra);
+            tree_rounds_kernel<false, WIDEST><<<1, kRoundThreads, round_lds, s>>>(ra);
         APPD_CHK();
     }
     e = launch_fallback<WIDEST>(W, n, out, w.ctrl, s);
     if (e != hipSuccess) return e;
+    tree_keyup_kernel<WIDEST><<<nb, 256, 0, s>>>(W, n, w.par, w.keyup, w.link, w.size,
+                                                 w.gcount, w.ctrl);
+    APPD_CHK();
+    tree_link_kernel<<<nb, 256, 0, s>>>(n, w.keyup, w.link, w.ctrl);
+    APPD_CHK();
+    tree_sizes_kernel<<<nb, 256, 0, s>>>(n, w.link, w.size, w.gcount, w.ctrl);
+    APPD_CHK();
+    tree_scan_kernel<<<1, kRoundThreads, 0, s>>>(n, w.gcount, w.gstart, w.gfill, w.tstart,
+                                                 w.ctrl);
+    APPD_CHK();
+    tree_group_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.gfill, w.grouped, w.rank,
+                                         w.ctrl);
+    APPD_CHK();
     tree_rank_kernel<<<1024, kRankTile, 0, s>>>(n, w.gcount, w.gstart, w.tstart, w.grouped,
                                                 w.keyup, w.rank, w.ctrl);
     APPD_CHK();
-    tree_presize_kernel<<<1, kRoundThreads, 0, s>>>(n, w.link, w.gstart, w.rank, w.size,
-                                                    w.sorted_size, w.sorted_grp, w.sorted_pre,
-                                                    w.ctrl);
+    tree_place_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.rank, w.size, w.sorted_size,
+                                         w.sorted_grp, w.ctrl);
+    APPD_CHK();
+    tree_segscan_kernel<<<1, kRoundThreads, 0, s>>>(n, w.sorted_size, w.sorted_grp,
+                                                    w.sorted_pre, w.ctrl);
     APPD_CHK();
     tree_pos_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.rank, w.sorted_pre, w.keyup, w.par,
                                        out, w.ctrl);

@@ -102,7 +102,7 @@ def main():
     import workloads
 
     n = args.n
-    W = workloads.config_mixture(n)
+    W = workloads.config_mixture(n) if n != 32768 else workloads.config_uniform(n)
     dev = torch.device("cuda:0")
     Wd = torch.from_numpy(W).to(dev)
     M = torch.empty((n, n), dtype=torch.float32, device=dev)

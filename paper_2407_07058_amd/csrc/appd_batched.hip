@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kBatchFillThreads) void fill_batched_kernel(
     float* __restrict__ M, int32_t* __restrict__ idx) {
     constexpr int NWV = kBatchFillThreads / kWave;
     __shared__ uint16_t s_sp[CB];
-    __shared__ uint16_t s_slot[CB];
+    __shared__ __align__(16) uint16_t s_slot[CB];
     __shared__ uint64_t s_gap[CB];
     __shared__ uint64_t s_R[NWV][CB];
     // which graph of this class, and which chunk of its rows
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBatchFillThreads) void fill_batched_kernel(
     __syncthreads();
     const int r0 = chunk * kBatchRows;
     const int r1 = min(n, r0 + kBatchRows);
-    fill_rows_block<CB, WIDEST>(pos, ek, n, 0, n, r0, r1, s_sp, s_slot, s_gap,
+    fill_rows_block<CB, WIDEST, false>(pos, ek, n, 0, n, r0, r1, s_sp, s_slot, s_gap,
                                 s_R[threadIdx.x / kWave], M + offsets[g], idx + offsets[g], NWV);
 }
 

@@ -77,8 +77,14 @@ __device__ __forceinline__ void fill_prep_block(const int32_t* __restrict__ pos,
 }
 
 // One column block, rows [r0, r1), waves of the workgroup take rows in turn.
-// s_R: this wave's row buffer of CB keys.
-template <int CB, bool WIDEST>
+// s_R: this wave's row buffer of CB keys.  Each lane owns the S = CB/64
+// consecutive slots k0..k0+S-1 and keeps their gap keys in registers for all
+// rows of the block.  Per row: the lane's running maxima within its own slots
+// (upward for slots at or above k*, downward below it), a cross-lane scan of the
+// lane totals, then the combined values go to s_R and are gathered in column
+// order.  VEC: rows are 16-byte aligned (n % 4 == 0), so each lane writes four
+// consecutive columns of M and of idx with one 16-byte store each.
+template <int CB, bool WIDEST, bool VEC>
 __device__ __forceinline__ void fill_rows_block(const int32_t* __restrict__ pos,
                                                 const uint64_t* __restrict__ ek, int n,
                                                 int j0, int cnt, int r0, int r1,
@@ -90,82 +96,103 @@ __device__ __forceinline__ void fill_rows_block(const int32_t* __restrict__ pos,
     static_assert(S >= 1 && S <= kWave, "CB must be in [64, 4096]");
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
-    for (int i = r0 + wid; i < r1; i += nwaves) {
-        const int a = pos[i];
+    const int k0 = lane * S;
+    uint64_t g[S];  // gap[k0 + q]; padding slots hold 0
+#pragma unroll
+    for (int q = 0; q < S; ++q) g[q] = s_gap[k0 + q];
+    uint64_t gnx = shfl_down_u64(g[0], 1);  // gap[k0 + S]
+    if (lane == kWave - 1) gnx = 0;
+    const int sp_last = s_sp[k0 + S - 1];   // padded slots hold 0xffff
+
+    int i = r0 + wid;
+    int a_next = i < r1 ? pos[i] : 0;
+    for (; i < r1; i += nwaves) {
+        const int a = a_next;
+        if (i + nwaves < r1) a_next = pos[i + nwaves];
         // k* = number of slots whose position is below a
-        const int last = lane * S + S - 1;
-        const bool below = s_sp[last] < a;  // padded slots hold 0xffff
-        const int nbl = __popcll(__ballot(below));
+        const int nbl = __popcll(__ballot(sp_last < a));
         const int base = nbl * S;
         const bool part = (lane < S) && (base + lane < CB) && (s_sp[min(base + lane, CB - 1)] < a);
         const int ks = base + __popcll(__ballot(part));
         const bool diag = ks < cnt && (int)s_sp[ks] == a;
 
+        // keys crossed next to the row's own position
         uint64_t bl = 0, br = 0;
         if (diag) {
             bl = ks > 0 ? s_gap[ks] : 0ull;
         } else {
             const int lo = ks > 0 ? (int)s_sp[ks - 1] + 1 : a + 1;
             const int hi = ks < cnt ? (int)s_sp[ks] : a;
-            for (int s = lo + lane; s <= hi; s += kWave) {
-                const uint64_t e = ek[s];
-                if (s <= a) bl = umax64(bl, e);
+            for (int x = lo + lane; x <= hi; x += kWave) {
+                const uint64_t e = ek[x];
+                if (x <= a) bl = umax64(bl, e);
                 else br = umax64(br, e);
             }
             bl = wave_max_u64(bl);
             br = wave_max_u64(br);
         }
+        const uint64_t brk = diag ? 0ull : br;
 
-        // E[k]: the key crossed when stepping from slot k toward the row
-        // (k >= k*: the step from slot k-1, or from a, to slot k;
-        //  k <  k*: the step from slot k to slot k+1, or to a).
-        auto E = [&](int k) -> uint64_t {
-            if (k > ks) return k < cnt ? s_gap[k] : 0ull;
-            if (k == ks) return diag ? 0ull : br;
-            if (k == ks - 1) return bl;
-            return s_gap[k + 1];
-        };
-        const int k0 = lane * S;
-        uint64_t up = 0, dn = 0;
+        // lane-local running maxima: upward over slots >= k*, downward below
+        uint64_t loc[S];
+        uint64_t run = 0;
 #pragma unroll
         for (int q = 0; q < S; ++q) {
             const int k = k0 + q;
-            const uint64_t e = E(k);
-            if (k >= ks) up = umax64(up, e);
-            else dn = umax64(dn, e);
+            const uint64_t e = k > ks ? g[q] : (k == ks ? brk : 0ull);
+            run = umax64(run, e);
+            loc[q] = run;
         }
-        uint64_t up_in = wave_incl_max_up(up, lane);
-        up_in = shfl_up_u64(up_in, 1);
-        if (lane == 0) up_in = 0;
-        uint64_t dn_in = wave_incl_max_down(dn, lane);
-        dn_in = shfl_down_u64(dn_in, 1);
-        if (lane == kWave - 1) dn_in = 0;
-        uint64_t run = up_in;
-#pragma unroll
-        for (int q = 0; q < S; ++q) {
-            const int k = k0 + q;
-            if (k >= ks) {
-                run = umax64(run, E(k));
-                s_R[k] = run;
-            }
-        }
-        run = dn_in;
+        const uint64_t up_tot = run;
+        run = 0;
 #pragma unroll
         for (int q = S - 1; q >= 0; --q) {
             const int k = k0 + q;
-            if (k < ks) {
-                run = umax64(run, E(k));
-                s_R[k] = run;
-            }
+            const uint64_t nxt = q + 1 < S ? g[q + 1] : gnx;
+            const uint64_t e = k < ks - 1 ? nxt : (k == ks - 1 ? bl : 0ull);
+            run = umax64(run, e);
+            if (k < ks) loc[q] = run;
+        }
+        const uint64_t dn_tot = run;
+        uint64_t up_in = wave_incl_max_up(up_tot, lane);
+        up_in = shfl_up_u64(up_in, 1);
+        if (lane == 0) up_in = 0;
+        uint64_t dn_in = wave_incl_max_down(dn_tot, lane);
+        dn_in = shfl_down_u64(dn_in, 1);
+        if (lane == kWave - 1) dn_in = 0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int k = k0 + q;
+            s_R[k] = umax64(loc[q], k >= ks ? up_in : dn_in);
         }
         wave_lds_sync();
 
         float* mrow = M + (size_t)i * (size_t)n + j0;
         int32_t* irow = idx + (size_t)i * (size_t)n + j0;
-        for (int c = lane; c < cnt; c += kWave) {
-            const uint64_t key = s_R[s_slot[c]];
-            mrow[c] = key ? key_weight<WIDEST>(key) : 0.0f;
-            irow[c] = key ? (int32_t)(uint32_t)key : -1;
+        if (VEC) {
+            for (int c = lane * 4; c < cnt; c += kWave * 4) {
+                const uint64_t sl = *(const uint64_t*)(s_slot + c);  // 4 slots
+                float4 mv;
+                int4 iv;
+                const uint64_t k0v = s_R[sl & 0xffff], k1v = s_R[(sl >> 16) & 0xffff];
+                const uint64_t k2v = s_R[(sl >> 32) & 0xffff], k3v = s_R[sl >> 48];
+                mv.x = k0v ? key_weight<WIDEST>(k0v) : 0.0f;
+                mv.y = k1v ? key_weight<WIDEST>(k1v) : 0.0f;
+                mv.z = k2v ? key_weight<WIDEST>(k2v) : 0.0f;
+                mv.w = k3v ? key_weight<WIDEST>(k3v) : 0.0f;
+                iv.x = k0v ? (int32_t)(uint32_t)k0v : -1;
+                iv.y = k1v ? (int32_t)(uint32_t)k1v : -1;
+                iv.z = k2v ? (int32_t)(uint32_t)k2v : -1;
+                iv.w = k3v ? (int32_t)(uint32_t)k3v : -1;
+                *(float4*)(mrow + c) = mv;
+                *(int4*)(irow + c) = iv;
+            }
+        } else {
+            for (int c = lane; c < cnt; c += kWave) {
+                const uint64_t key = s_R[s_slot[c]];
+                mrow[c] = key ? key_weight<WIDEST>(key) : 0.0f;
+                irow[c] = key ? (int32_t)(uint32_t)key : -1;
+            }
         }
         wave_lds_sync();
     }

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kFillThreads) void fill_prep_kernel(const int32_t* 
     fill_prep_block<CB>(pos, ek, n, blockIdx.x, blk_sp, blk_slot, blk_gap, keys);
 }
 
-template <int CB, bool WIDEST>
+template <int CB, bool WIDEST, bool VEC>
 __global__ __launch_bounds__(kFillThreads) void fill_kernel(
     const int32_t* __restrict__ pos, const uint64_t* __restrict__ ek, int n,
     const uint16_t* __restrict__ blk_sp, const uint16_t* __restrict__ blk_slot,
@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kFillThreads) void fill_kernel(
     int rows_per_wg) {
     constexpr int NWV = kFillThreads / kWave;
     __shared__ uint16_t s_sp[CB];
-    __shared__ uint16_t s_slot[CB];
+    __shared__ __align__(16) uint16_t s_slot[CB];
     __shared__ uint64_t s_gap[CB];
     __shared__ uint64_t s_R[NWV][CB];
     const int j0 = blockIdx.x * CB;
@@ -51,8 +51,8 @@ __global__ __launch_bounds__(kFillThreads) void fill_kernel(
     __syncthreads();
     const int r0 = blockIdx.y * rows_per_wg;
     const int r1 = min(n, r0 + rows_per_wg);
-    fill_rows_block<CB, WIDEST>(pos, ek, n, j0, cnt, r0, r1, s_sp, s_slot, s_gap,
-                                s_R[threadIdx.x / kWave], M, idx, NWV);
+    fill_rows_block<CB, WIDEST, VEC>(pos, ek, n, j0, cnt, r0, r1, s_sp, s_slot, s_gap,
+                                     s_R[threadIdx.x / kWave], M, idx, NWV);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -131,8 +131,13 @@ static hipError_t run_fill_t(int n, float* M, int32_t* idx, const SingleWs& w, h
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 grid(nb, (n + kFillRowsPerWG - 1) / kFillRowsPerWG);
-    fill_kernel<kFillCB, WIDEST><<<grid, kFillThreads, 0, s>>>(
-        w.pos, w.ek, n, w.blk_sp, w.blk_slot, w.blk_gap, M, idx, kFillRowsPerWG);
+    const bool vec = (n % 4 == 0) && (((uintptr_t)M | (uintptr_t)idx) & 15u) == 0;
+    if (vec)
+        fill_kernel<kFillCB, WIDEST, true><<<grid, kFillThreads, 0, s>>>(
+            w.pos, w.ek, n, w.blk_sp, w.blk_slot, w.blk_gap, M, idx, kFillRowsPerWG);
+    else
+        fill_kernel<kFillCB, WIDEST, false><<<grid, kFillThreads, 0, s>>>(
+            w.pos, w.ek, n, w.blk_sp, w.blk_slot, w.blk_gap, M, idx, kFillRowsPerWG);
     return hipGetLastError();
 }
 

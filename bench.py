@@ -1,18 +1,28 @@
 #!/usr/bin/env python3
 """APPD benchmark on one MI355X.
 
-Workload: one complete graph of n = 8192 points in R^16 drawn from a
+Headline workload: one complete graph of n = 8192 points in R^16 drawn from a
 10-component Gaussian mixture (centres uniform in [0,1]^16, sigma 0.05, seed 2);
 float32 Euclidean weights (computed in float64, rounded once), so W is 256 MiB.
-A step is one whole forward -- spanning tree + calculation-and-copy fill --
-writing the float32 M and int32 idx matrices, with W already resident in HBM.
+A step is one whole forward -- spanning tree, attachment order and the
+calculation-and-copy fill -- through appd_forward_ex, writing the float32 M and
+int32 idx matrices, with W already resident in HBM.  `value` is n^2 entries per
+second over the timed steps.
 
-Prints one JSON line: entries/s (n^2 per second) as `value`, the achieved
-algorithmic HBM rate, per-phase times from HIP events recorded on the stream the
-kernels run on, the roofline of the dominant kernel and the CPU oracle timed on
-the host as a reference point.
+Beside it, on the same GPU:
+  batched  -- 4096 graphs, n log-uniform in [16, 1024], points uniform in
+              [0,1]^d, d in {2, 8}: the batched forward replayed from a HIP graph
+              against a loop of single-graph forward calls;
+  fwd_bwd  -- 256 graphs, n uniform in {64..2048}, X ~ N(0, I_8), upstream
+              gradient G ~ N(0, 1): point-to-graph weights, forward and backward
+              to the points, batched against a per-graph loop.
+The roofline entry describes the kernel that takes the most time per headline
+step; its launches are bracketed by HIP events on the library's launch stream
+(appd_timer_*) inside the timed region.  The CPU oracle (plain Algorithm 4, one
+thread) is timed on the host as a reference point.
 """
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -23,6 +33,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
+K_LIST = 16             # candidate-list length of the parallel tree (appd_tree.hip)
+
+CSRC = "paper_2407_07058_amd/csrc/"
+KERNEL_SOURCES = {
+    "fill_kernel": [CSRC + "appd_fill.h", CSRC + "appd_device.h", CSRC + "appd_single.hip"],
+    "tree_pass_kernel": [CSRC + "appd_tree.hip", CSRC + "appd_device.h"],
+    "tree_rounds_kernel": [CSRC + "appd_tree.hip", CSRC + "appd_device.h"],
+    "prim_single_kernel": [CSRC + "appd_prim.h", CSRC + "appd_device.h",
+                           CSRC + "appd_single.hip"],
+}
+
+
+def alg_bytes_per_launch(kernel, n):
+    """Algorithmic HBM bytes one launch of `kernel` moves for one n-vertex graph."""
+    return {
+        "fill_kernel": 8.0 * n * n,          # M (fp32) + idx (int32) written once
+        "tree_pass_kernel": 4.0 * n * n,     # W read once
+        "prim_single_kernel": 4.0 * n * n,   # W read once (one row per Prim step)
+        # candidate lists (K u64 per vertex) + list pointers, labels, parents
+        "tree_rounds_kernel": (8.0 * K_LIST + 12.0) * n,
+    }.get(kernel)
 
 
 def source_sha(paths):
@@ -33,24 +64,17 @@ def source_sha(paths):
     return h.hexdigest()[:16]
 
 
-KERNEL_SOURCES = {
-    "prim_single_kernel": ["paper_2407_07058_amd/csrc/appd_prim.h",
-                           "paper_2407_07058_amd/csrc/appd_device.h",
-                           "paper_2407_07058_amd/csrc/appd_single.hip"],
-    "fill_kernel": ["paper_2407_07058_amd/csrc/appd_fill.h",
-                    "paper_2407_07058_amd/csrc/appd_device.h",
-                    "paper_2407_07058_amd/csrc/appd_single.hip"],
-}
-
-
-def measured_traffic(kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when it is missing or was taken on a different version of the kernel."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's
+    readings) from the committed rocprofv3 counter summary, or None when missing
+    or taken on a different version of the kernel's sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
         return None
     rec = json.load(open(path)).get(kernel)
-    if not rec or rec.get("source_sha") != source_sha(KERNEL_SOURCES[kernel]):
+    if not rec or rec.get("workload") != workload:
+        return None
+    if rec.get("source_sha") != source_sha(KERNEL_SOURCES[kernel]):
         return None
     return rec.get("bytes_per_launch")
 
@@ -70,6 +94,213 @@ def cpu_baseline(W, n, runs=3):
                       "(plain Algorithm 4), median %.2f s" % (n, runs, t)}
 
 
+def elapsed(a, b):
+    return a.elapsed_time(b)
+
+
+def bench_single(appd, torch, W, n, steps, warmup):
+    dev = torch.device("cuda:0")
+    Wd = torch.from_numpy(W).to(dev)
+    M = torch.empty((n, n), dtype=torch.float32, device=dev)
+    I = torch.empty((n, n), dtype=torch.int32, device=dev)
+    ws = torch.empty(appd.workspace_bytes(n), dtype=torch.uint8, device=dev)
+
+    def step():
+        appd.forward(Wd, out=(M, I), workspace=ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    # kernel census (untimed): every launch bracketed, two steps
+    census = {}
+    with appd.LaunchTimer("*") as tm:
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        for name in tm.names():
+            cnt, tot, _ = tm.read(name)
+            census[name] = {"launches_per_step": cnt / 2.0, "ms_per_step": tot / 2.0,
+                            "avg_launch_ms": tot / max(cnt, 1)}
+    dominant = max(census, key=lambda k: census[k]["ms_per_step"])
+
+    # timed region: only the dominant kernel's launches are bracketed
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    with appd.LaunchTimer(dominant) as tm:
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(steps):
+            step()
+        t1.record()
+        torch.cuda.synchronize()
+        launches, kern_ms, overflow = tm.read()
+    ms = elapsed(t0, t1) / steps
+    assert not overflow and launches > 0
+    avg_launch_ms = kern_ms / launches
+    return Wd, ms, census, dominant, launches / steps, avg_launch_ms
+
+
+def bench_batched(appd, torch, steps):
+    """4096 ragged graphs: batched forward (HIP graph replay) vs per-graph loop."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import workloads
+    with ThreadPoolExecutor(8) as ex:
+        Ws = list(ex.map(workloads.euclid_w, workloads.ragged_points()))
+    flat, offsets, ns = workloads.pack(Ws)
+    del Ws
+    dev = torch.device("cuda:0")
+    b = appd.Batch(ns, dev)
+    Wd = torch.from_numpy(flat).to(dev)
+    del flat
+    M = torch.empty_like(Wd)
+    I = torch.empty(Wd.numel(), dtype=torch.int32, device=dev)
+    entries = float(b.total_nn)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.forward(Wd, out=(M, I))
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.forward(Wd, out=(M, I))
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        graph.replay()
+    t1.record()
+    torch.cuda.synchronize()
+    ms_b = elapsed(t0, t1) / steps
+    Mb = M.clone()
+    Ib = I.clone()
+
+    # per-graph loop: one appd_forward_ws call per graph, same stream, same buffers
+    L = appd.lib()
+    wsz = max(appd.workspace_bytes(int(n)) for n in ns)
+    ws = torch.empty(wsz, dtype=torch.uint8, device=dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    wp, mp, ip, sp = Wd.data_ptr(), M.data_ptr(), I.data_ptr(), ws.data_ptr()
+    calls = [(ctypes.c_void_p(wp + 4 * int(o)), int(n), ctypes.c_void_p(mp + 4 * int(o)),
+              ctypes.c_void_p(ip + 4 * int(o))) for o, n in zip(offsets, ns)]
+    fwd = L.appd_forward_ws
+
+    def loop():
+        for w, n, m, i in calls:
+            rc = fwd(w, n, m, i, ctypes.c_void_p(sp), wsz, stream)
+            if rc:
+                raise RuntimeError("appd_forward_ws failed (%d)" % rc)
+
+    loop()
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        loop()
+    t1.record()
+    torch.cuda.synchronize()
+    ms_l = elapsed(t0, t1) / steps
+    same = bool(torch.equal(M, Mb) and torch.equal(I, Ib))
+    return {"workload": "4096 graphs, n log-uniform in [16,1024] (sum n^2 = %d), points "
+                        "uniform in [0,1]^d, d in {2,8}, seed 4; fp32 Euclidean W packed "
+                        "in HBM" % b.total_nn,
+            "entries": entries,
+            "batched_ms": ms_b, "batched_entries_per_s": entries / ms_b * 1e3,
+            "batched_alg_gbps": 12.0 * entries / ms_b / 1e6,
+            "loop_ms": ms_l, "loop_entries_per_s": entries / ms_l * 1e3,
+            "speedup_vs_loop": ms_l / ms_b,
+            "batched": "one prepared plan, kernels replayed from a HIP graph",
+            "loop": "%d appd_forward_ws calls on one stream" % len(ns),
+            "outputs_identical": same}
+
+
+def bench_fwd_bwd(appd, torch, steps):
+    """256 graphs: W from X + forward + backward to X, batched vs per-graph loop."""
+    import numpy as np
+
+    import workloads
+    items = workloads.diff_batch()
+    ns = np.array([x.shape[0] for x, _ in items], np.int32)
+    d = 8
+    dev = torch.device("cuda:0")
+    b = appd.Batch(ns, dev)
+    X = torch.from_numpy(np.concatenate([x for x, _ in items])).to(dev).contiguous()
+    G = torch.from_numpy(np.concatenate([g.ravel() for _, g in items])).to(dev)
+    del items
+    W = torch.empty(b.total_nn, dtype=torch.float32, device=dev)
+    M = torch.empty_like(W)
+    I = torch.empty(b.total_nn, dtype=torch.int32, device=dev)
+    entries = float(b.total_nn)
+
+    def batched():
+        b.pairwise(X, d, out=W)
+        _, _, parent = b.forward(W, out=(M, I), return_parent=True)
+        return b.backward_points(X, d, W, G, I, parent)
+
+    dXb = batched()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        batched()
+    t1.record()
+    torch.cuda.synchronize()
+    ms_b = elapsed(t0, t1) / steps
+
+    L = appd.lib()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    fsz = max(appd.workspace_bytes(int(n)) for n in ns)
+    gsz = max(int(L.appd_grad_workspace_bytes(int(n))) for n in ns)
+    fws = torch.empty(fsz, dtype=torch.uint8, device=dev)
+    gws = torch.empty(gsz, dtype=torch.uint8, device=dev)
+    parent = torch.empty(b.total_n, dtype=torch.int32, device=dev)
+    dX = torch.empty(b.total_n * d, dtype=torch.float32, device=dev)
+    P = ctypes.c_void_p
+    xp, wp, mp, ip, gp = X.data_ptr(), W.data_ptr(), M.data_ptr(), I.data_ptr(), G.data_ptr()
+    pp, dp = parent.data_ptr(), dX.data_ptr()
+    calls = []
+    for g, n in enumerate(ns):
+        o, no = int(b.offsets[g]), int(b.noff[g])
+        calls.append((int(n), P(xp + 4 * d * no), P(wp + 4 * o), P(mp + 4 * o), P(ip + 4 * o),
+                      P(gp + 4 * o), P(pp + 4 * no), P(dp + 4 * d * no)))
+
+    def loop():
+        for n, x, w, m, i, gg, par, dx in calls:
+            rc = L.appd_pairwise_euclidean(x, n, d, w, P(gws.data_ptr()), gsz, stream)
+            rc = rc or L.appd_forward_ex(w, n, 0, m, i, None, par, P(fws.data_ptr()), fsz, stream)
+            rc = rc or L.appd_backward_points(x, n, d, w, gg, i, par, dx, P(gws.data_ptr()), gsz,
+                                              stream)
+            if rc:
+                raise RuntimeError("per-graph call failed (%d)" % rc)
+
+    loop()
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        loop()
+    t1.record()
+    torch.cuda.synchronize()
+    ms_l = elapsed(t0, t1) / steps
+    err = float((dX - dXb).abs().max() / dXb.abs().max().clamp_min(1e-30))
+    return {"workload": "256 graphs, n uniform in {64..2048} (sum n^2 = %d), X ~ N(0, I_8) "
+                        "fp32, G ~ N(0,1) fp32, seed 5" % b.total_nn,
+            "entries": entries,
+            "batched_ms": ms_b, "batched_entries_per_s": entries / ms_b * 1e3,
+            "loop_ms": ms_l, "loop_entries_per_s": entries / ms_l * 1e3,
+            "speedup_vs_loop": ms_l / ms_b,
+            "alg_bytes": "W build 4n^2 + forward 12n^2 + backward 8n^2 per graph",
+            "batched_alg_gbps": 24.0 * entries / ms_b / 1e6,
+            "loop": "%d x (appd_pairwise_euclidean, appd_forward_ex, appd_backward_points)"
+                    % len(ns),
+            "dX_rel_diff_loop_vs_batched": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +308,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batches", action="store_true",
+                    help="skip the batched and forward+backward comparisons")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -91,76 +324,51 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": max(args.steps, 1)}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this APPD build runs a graph on a single "
-              "MI355X and has no multi-GPU path (got --gpus %d)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only: this APPD build runs on a single MI355X and "
+              "has no multi-GPU path (got --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2407_07058_amd as appd
     import workloads
 
     n = args.n
-    W = workloads.config_mixture(n) if n != 32768 else workloads.config_uniform(n)
-    dev = torch.device("cuda:0")
-    Wd = torch.from_numpy(W).to(dev)
-    M = torch.empty((n, n), dtype=torch.float32, device=dev)
-    I = torch.empty((n, n), dtype=torch.int32, device=dev)
-    ws = torch.empty(appd.workspace_bytes(n), dtype=torch.uint8, device=dev)
-
-    def step():
-        appd.tree(Wd, ws)
-        appd.fill(n, ws, M, I)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record()
-    for k in range(K):
-        ev[k][0].record()
-        appd.tree(Wd, ws)
-        ev[k][1].record()
-        appd.fill(n, ws, M, I)
-        ev[k][2].record()
-    t_stop.record()
-    torch.cuda.synchronize()
-    total_ms = t_start.elapsed_time(t_stop)
-    ms = total_ms / K
-    tree_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
-    fill_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    if n == 8192:
+        W = workloads.config_mixture(n)
+        wl = ("single complete graph, n=8192 points in R^16 from a 10-component Gaussian "
+              "mixture (sigma 0.05, seed 2); fp32 Euclidean W resident in HBM; outputs fp32 M "
+              "+ int32 idx")
+    elif n == 32768:
+        W = workloads.config_uniform(n)
+        wl = ("single dense graph, n=32768, upper triangle iid uniform(0,1) fp32 (seed 3), "
+              "mirrored, zero diagonal; outputs fp32 M + int32 idx")
+    else:
+        W = workloads.config_mixture(n)
+        wl = "single complete graph, n=%d points from the 10-component mixture (seed 2)" % n
+    wl_key = "single-%d" % n
+    print("step single-graph forward n=%d" % n, file=sys.stderr, flush=True)
+    Wd, ms, census, dom, dom_launches, dom_ms = bench_single(appd, torch, W, n, args.steps,
+                                                            args.warmup)
+    del Wd
+    torch.cuda.empty_cache()
 
     entries = float(n) * n
-    alg_bytes = 12.0 * n * n  # W read + M write + idx write
-    phases = {
-        "tree": {"kernel": "prim_single_kernel", "ms": tree_ms,
-                 "alg_bytes": 4.0 * n * n,
-                 "alg_gbps": 4.0 * n * n / tree_ms / 1e6,
-                 "ns_per_prim_step": tree_ms * 1e6 / max(n - 1, 1)},
-        "fill": {"kernel": "fill_prep_kernel+fill_kernel", "ms": fill_ms,
-                 "alg_bytes": 8.0 * n * n,
-                 "alg_gbps": 8.0 * n * n / fill_ms / 1e6},
-    }
-    dom = "tree" if tree_ms >= fill_ms else "fill"
-    dk = "prim_single_kernel" if dom == "tree" else "fill_kernel"
-    achieved = phases[dom]["alg_gbps"]
-    roofline = {"bound": "hbm", "kernel": dk, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                "traffic": measured_traffic(dk),
-                "alg_bytes_per_launch": phases[dom]["alg_bytes"]}
+    alg = alg_bytes_per_launch(dom, n)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": None, "traffic": measured_traffic(dom, wl_key),
+                "alg_bytes_per_launch": alg, "launches_per_step": dom_launches,
+                "avg_launch_ms": dom_ms}
+    if alg is not None:
+        roofline["achieved"] = alg / dom_ms / 1e6
+        roofline["frac"] = roofline["achieved"] / HBM_PEAK_GBPS
 
     out = {
         "metric": "APPD entries/sec (n^2/s)",
         "value": entries / (ms / 1e3),
         "unit": "entries/s",
         "n_gpus": 1,
-        "steps": K,
+        "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
         "higher_is_better": True,
@@ -168,16 +376,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "single complete graph, n=%d points in R^16 from a "
-                               "10-component Gaussian mixture (sigma 0.05, seed 2); fp32 "
-                               "Euclidean W resident in HBM; outputs fp32 M + int32 idx" % n,
-                   "n": n, "mode": "minimax"},
-        "alg_hbm_gbps": alg_bytes / (ms / 1e3) / 1e9,
-        "phases": phases,
+        "config": {"workload": wl, "n": n, "mode": "minimax"},
+        "alg_hbm_gbps": 12.0 * entries / (ms / 1e3) / 1e9,
+        "alg_hbm_frac": 12.0 * entries / (ms / 1e3) / 1e9 / HBM_PEAK_GBPS,
+        "kernels": census,
         "roofline": roofline,
     }
+    if not args.no_batches:
+        print("step batched forward vs loop", file=sys.stderr, flush=True)
+        out["batched"] = bench_batched(appd, torch, 3)
+        torch.cuda.empty_cache()
+        print("step fwd+bwd vs loop", file=sys.stderr, flush=True)
+        out["fwd_bwd"] = bench_fwd_bwd(appd, torch, 3)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(W, n)
+        print("step cpu oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(W, n, runs=15 if n <= 8192 else 1)
     print(json.dumps(out), flush=True)
 
 

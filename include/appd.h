@@ -189,6 +189,23 @@ int appd_backward_points(const float* X, int n, int d, const float* W, const flo
 int appd_backward_w(const float* G, const int32_t* idx, const int32_t* parent, int n, float* dW,
                     void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------ timing
+ * Launch timer for measurement.  appd_timer_start(kernel, capacity) creates
+ * 2*capacity HIP events (the only allocation) and from then on brackets every
+ * launch of the named kernel (its base name, e.g. "fill_kernel"; "*" = every
+ * kernel) by two events recorded on the launch stream.  Launches beyond
+ * `capacity` are not recorded and set the overflow flag.  kernel == NULL stops
+ * the timer and destroys the events.  Not meant for code under HIP graph
+ * capture.  One timer per process (calls are serialised by a mutex).
+ * appd_timer_read waits for the recorded events of `kernel` and returns the
+ * number of launches and the sum of their durations.  appd_timer_names writes
+ * up to `capacity` distinct recorded kernel names (static strings) into
+ * `names` (nullable) and returns how many there are.
+ */
+int appd_timer_start(const char* kernel, int capacity);
+int appd_timer_read(const char* kernel, int* launches, double* total_ms, int* overflow);
+int appd_timer_names(const char** names, int capacity);
+
 #ifdef __cplusplus
 }
 #endif

@@ -52,6 +52,9 @@ SIGNATURES = {
     "appd_pairwise_euclidean": ([_P, _I, _I, _P, _P, _SZ, _P], _I),
     "appd_backward_points": ([_P, _I, _I, _P, _P, _P, _P, _P, _P, _SZ, _P], _I),
     "appd_backward_w": ([_P, _P, _P, _I, _P, _P, _SZ, _P], _I),
+    "appd_timer_start": ([ctypes.c_char_p, _I], _I),
+    "appd_timer_read": ([ctypes.c_char_p, _P, _P, _P], _I),
+    "appd_timer_names": ([_P, _I], _I),
 }
 
 BATCH_MAX_N = 2048
@@ -344,3 +347,40 @@ def appd_points(X: torch.Tensor):
 
 def appd_points_batched(X: torch.Tensor, batch: Batch, d: int):
     return APPDPointsBatched.apply(X, batch, d)
+
+
+class LaunchTimer:
+    """HIP events around every launch of one library kernel (appd_timer_*).
+
+    `kernel` is the kernel's base name ("fill_kernel", "tree_rounds_kernel", ...)
+    or "*" for all of them; the events are created here, so the region being
+    timed only records them.  read() waits for them."""
+
+    def __init__(self, kernel: str = "*", capacity: int = 4096):
+        _check(lib().appd_timer_start(kernel.encode(), capacity), "appd_timer_start")
+        self.kernel = kernel
+
+    def read(self, kernel: str = None):
+        """(launches, total milliseconds, overflowed) of `kernel` (default: the
+        timed kernel)."""
+        k = (kernel or self.kernel).encode()
+        cnt, tot, ovf = ctypes.c_int(), ctypes.c_double(), ctypes.c_int()
+        _check(lib().appd_timer_read(k, ctypes.byref(cnt), ctypes.byref(tot), ctypes.byref(ovf)),
+               "appd_timer_read")
+        return cnt.value, tot.value, bool(ovf.value)
+
+    def names(self):
+        n = lib().appd_timer_names(None, 0)
+        arr = (ctypes.c_char_p * max(n, 1))()
+        lib().appd_timer_names(ctypes.cast(arr, ctypes.c_void_p), n)
+        return [arr[i].decode() for i in range(n)]
+
+    def close(self):
+        _check(lib().appd_timer_start(None, 0), "appd_timer_start")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+

@@ -98,20 +98,24 @@ static hipError_t run_batched_t(const float* W, const int64_t* offsets, const in
         if (!count) continue;
         switch (c) {
             case 0:
-                prim_batched_kernel<64, 1, WIDEST><<<count, 64, 0, s>>>(W, offsets, ns, plan.perm,
-                                                                       plan.noff, first, tree);
+                APPD_LAUNCH("prim_batched_kernel", s,
+                    prim_batched_kernel<64, 1, WIDEST><<<count, 64, 0, s>>>(W, offsets, ns,
+                        plan.perm, plan.noff, first, tree));
                 break;
             case 1:
-                prim_batched_kernel<64, 4, WIDEST><<<count, 64, 0, s>>>(W, offsets, ns, plan.perm,
-                                                                       plan.noff, first, tree);
+                APPD_LAUNCH("prim_batched_kernel", s,
+                    prim_batched_kernel<64, 4, WIDEST><<<count, 64, 0, s>>>(W, offsets, ns,
+                        plan.perm, plan.noff, first, tree));
                 break;
             case 2:
-                prim_batched_kernel<256, 4, WIDEST><<<count, 256, 0, s>>>(
-                    W, offsets, ns, plan.perm, plan.noff, first, tree);
+                APPD_LAUNCH("prim_batched_kernel", s,
+                    prim_batched_kernel<256, 4, WIDEST><<<count, 256, 0, s>>>(W, offsets, ns,
+                        plan.perm, plan.noff, first, tree));
                 break;
             default:
-                prim_batched_kernel<256, 8, WIDEST><<<count, 256, 0, s>>>(
-                    W, offsets, ns, plan.perm, plan.noff, first, tree);
+                APPD_LAUNCH("prim_batched_kernel", s,
+                    prim_batched_kernel<256, 8, WIDEST><<<count, 256, 0, s>>>(W, offsets, ns,
+                        plan.perm, plan.noff, first, tree));
                 break;
         }
         hipError_t e = hipGetLastError();
@@ -124,24 +128,24 @@ static hipError_t run_batched_t(const float* W, const int64_t* offsets, const in
         const int blocks = plan.class_chunks[c];
         switch (c) {
             case 0:
-                fill_batched_kernel<64, WIDEST><<<blocks, kBatchFillThreads, 0, s>>>(
-                    offsets, ns, plan.perm, plan.noff, plan.chunk_start, first, count, tree, M,
-                    idx);
+                APPD_LAUNCH("fill_batched_kernel", s,
+                    fill_batched_kernel<64, WIDEST><<<blocks, kBatchFillThreads, 0, s>>>(offsets,
+                        ns, plan.perm, plan.noff, plan.chunk_start, first, count, tree, M, idx));
                 break;
             case 1:
-                fill_batched_kernel<256, WIDEST><<<blocks, kBatchFillThreads, 0, s>>>(
-                    offsets, ns, plan.perm, plan.noff, plan.chunk_start, first, count, tree, M,
-                    idx);
+                APPD_LAUNCH("fill_batched_kernel", s,
+                    fill_batched_kernel<256, WIDEST><<<blocks, kBatchFillThreads, 0, s>>>(offsets,
+                        ns, plan.perm, plan.noff, plan.chunk_start, first, count, tree, M, idx));
                 break;
             case 2:
-                fill_batched_kernel<1024, WIDEST><<<blocks, kBatchFillThreads, 0, s>>>(
-                    offsets, ns, plan.perm, plan.noff, plan.chunk_start, first, count, tree, M,
-                    idx);
+                APPD_LAUNCH("fill_batched_kernel", s,
+                    fill_batched_kernel<1024, WIDEST><<<blocks, kBatchFillThreads, 0, s>>>(offsets,
+                        ns, plan.perm, plan.noff, plan.chunk_start, first, count, tree, M, idx));
                 break;
             default:
-                fill_batched_kernel<2048, WIDEST><<<blocks, kBatchFillThreads, 0, s>>>(
-                    offsets, ns, plan.perm, plan.noff, plan.chunk_start, first, count, tree, M,
-                    idx);
+                APPD_LAUNCH("fill_batched_kernel", s,
+                    fill_batched_kernel<2048, WIDEST><<<blocks, kBatchFillThreads, 0, s>>>(offsets,
+                        ns, plan.perm, plan.noff, plan.chunk_start, first, count, tree, M, idx));
                 break;
         }
         hipError_t e = hipGetLastError();

@@ -185,8 +185,9 @@ hipError_t run_pairwise(const float* X, const int64_t* xoff, const int64_t* offs
                         int total_tiles, int d, float* W, hipStream_t s) {
     if (d < 1 || d > kMaxD) return hipErrorInvalidValue;
     if (total_tiles == 0) return hipSuccess;
-    pairwise_kernel<<<total_tiles, kPairThreads, 0, s>>>(X, xoff, offsets, ns, tile_start,
-                                                        num_graphs, d, W);
+    APPD_LAUNCH("pairwise_kernel", s,
+        pairwise_kernel<<<total_tiles, kPairThreads, 0, s>>>(X, xoff, offsets, ns, tile_start,
+            num_graphs, d, W));
     return hipGetLastError();
 }
 
@@ -201,8 +202,9 @@ hipError_t run_edge_grad(const float* G, const int32_t* idx, const int64_t* offs
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    edge_grad_kernel<<<total_chunks, 256, lds, s>>>(G, idx, offsets, noff, ns, parent,
-                                                   chunk_start, num_graphs, rows_per_wg, gedge);
+    APPD_LAUNCH("edge_grad_kernel", s,
+        edge_grad_kernel<<<total_chunks, 256, lds, s>>>(G, idx, offsets, noff, ns, parent,
+            chunk_start, num_graphs, rows_per_wg, gedge));
     return hipGetLastError();
 }
 
@@ -211,8 +213,9 @@ hipError_t run_chain(const float* X, const int64_t* xoff, const float* W, const 
                      const float* gedge, const int32_t* vstart, int num_graphs, int total_vblocks,
                      int d, float* dX, hipStream_t s) {
     if (total_vblocks == 0) return hipSuccess;
-    chain_points_kernel<<<total_vblocks, 256, 0, s>>>(X, xoff, W, offsets, noff, ns, parent,
-                                                     gedge, vstart, num_graphs, d, dX);
+    APPD_LAUNCH("chain_points_kernel", s,
+        chain_points_kernel<<<total_vblocks, 256, 0, s>>>(X, xoff, W, offsets, noff, ns, parent,
+            gedge, vstart, num_graphs, d, dX));
     return hipGetLastError();
 }
 
@@ -227,7 +230,8 @@ hipError_t run_zero(void* p, size_t bytes, hipStream_t s) {
     const size_t words = bytes / 4;
     if (!words) return hipSuccess;
     const size_t blocks = (words + 255) / 256;
-    zero_kernel<<<(unsigned)(blocks < 8192 ? blocks : 8192), 256, 0, s>>>((uint32_t*)p, words);
+    APPD_LAUNCH("zero_kernel", s,
+        zero_kernel<<<(unsigned)(blocks < 8192 ? blocks : 8192), 256, 0, s>>>((uint32_t*)p, words));
     return hipGetLastError();
 }
 
@@ -239,7 +243,8 @@ __global__ void scale_offsets_kernel(const int64_t* __restrict__ noff, int num_g
 
 hipError_t run_scale_offsets(const int64_t* noff, int num_graphs, int d, int64_t* xoff,
                              hipStream_t s) {
-    scale_offsets_kernel<<<(num_graphs + 255) / 256, 256, 0, s>>>(noff, num_graphs, d, xoff);
+    APPD_LAUNCH("scale_offsets_kernel", s,
+        scale_offsets_kernel<<<(num_graphs + 255) / 256, 256, 0, s>>>(noff, num_graphs, d, xoff));
     return hipGetLastError();
 }
 
@@ -258,7 +263,9 @@ __global__ void single_table_kernel(int n, int32_t* ns, int64_t* offsets, int64_
 hipError_t run_single_table(int n, int32_t* ns, int64_t* offsets, int64_t* noff,
                             int32_t* tile_start, int32_t* gchunk_start, int32_t* vstart,
                             hipStream_t s) {
-    single_table_kernel<<<1, 64, 0, s>>>(n, ns, offsets, noff, tile_start, gchunk_start, vstart);
+    APPD_LAUNCH("single_table_kernel", s,
+        single_table_kernel<<<1, 64, 0, s>>>(n, ns, offsets, noff, tile_start, gchunk_start,
+            vstart));
     return hipGetLastError();
 }
 
@@ -275,7 +282,8 @@ __global__ void edge_to_w_kernel(const float* __restrict__ gedge, const int32_t*
 
 hipError_t run_edge_to_w(const float* gedge, const int32_t* parent, int n, float* dW,
                          hipStream_t s) {
-    edge_to_w_kernel<<<(n + 255) / 256, 256, 0, s>>>(gedge, parent, n, dW);
+    APPD_LAUNCH("edge_to_w_kernel", s,
+        edge_to_w_kernel<<<(n + 255) / 256, 256, 0, s>>>(gedge, parent, n, dW));
     return hipGetLastError();
 }
 

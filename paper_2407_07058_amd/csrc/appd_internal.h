@@ -9,6 +9,19 @@ namespace appd {
 
 void set_last_error(int code);
 
+// Launch timer (appd_timer_start): events around the launches of the selected
+// kernel, recorded on the launch stream.  Off by default: one relaxed load.
+bool timer_wants(const char* name);
+void timer_begin(const char* name, hipStream_t s);
+void timer_end(hipStream_t s);
+#define APPD_LAUNCH(name, stream, ...)                        \
+    do {                                                      \
+        const bool appd_timed_ = ::appd::timer_wants(name);   \
+        if (appd_timed_) ::appd::timer_begin(name, (stream)); \
+        __VA_ARGS__;                                          \
+        if (appd_timed_) ::appd::timer_end(stream);           \
+    } while (0)
+
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Carved single-graph workspace (device pointers).

@@ -61,7 +61,8 @@ static hipError_t launch_prim(const float* W, int n, PrimOut out, hipStream_t s)
     const int ch = (n + kPrimThreads - 1) / kPrimThreads;
 #define APPD_PRIM_CASE(C)                                                                    \
     if (ch <= C) {                                                                           \
-        prim_single_kernel<C, WIDEST><<<1, kPrimThreads, 0, s>>>(W, n, out);                 \
+        APPD_LAUNCH("prim_single_kernel", s,                                                 \
+                    prim_single_kernel<C, WIDEST><<<1, kPrimThreads, 0, s>>>(W, n, out));    \
         return hipGetLastError();                                                            \
     }
     APPD_PRIM_CASE(1)
@@ -126,18 +127,21 @@ bool valid_mode(int mode) {
 template <bool WIDEST>
 static hipError_t run_fill_t(int n, float* M, int32_t* idx, const SingleWs& w, hipStream_t s) {
     const int nb = fill_blocks(n);
-    fill_prep_kernel<kFillCB><<<nb, kFillThreads, 0, s>>>(w.pos, w.ek, n, w.blk_sp, w.blk_slot,
-                                                         w.blk_gap);
+    APPD_LAUNCH("fill_prep_kernel", s,
+        fill_prep_kernel<kFillCB><<<nb, kFillThreads, 0, s>>>(w.pos, w.ek, n, w.blk_sp, w.blk_slot,
+            w.blk_gap));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 grid(nb, (n + kFillRowsPerWG - 1) / kFillRowsPerWG);
     const bool vec = (n % 4 == 0) && (((uintptr_t)M | (uintptr_t)idx) & 15u) == 0;
     if (vec)
-        fill_kernel<kFillCB, WIDEST, true><<<grid, kFillThreads, 0, s>>>(
-            w.pos, w.ek, n, w.blk_sp, w.blk_slot, w.blk_gap, M, idx, kFillRowsPerWG);
+        APPD_LAUNCH("fill_kernel", s,
+            fill_kernel<kFillCB, WIDEST, true><<<grid, kFillThreads, 0, s>>>(w.pos, w.ek, n,
+                w.blk_sp, w.blk_slot, w.blk_gap, M, idx, kFillRowsPerWG));
     else
-        fill_kernel<kFillCB, WIDEST, false><<<grid, kFillThreads, 0, s>>>(
-            w.pos, w.ek, n, w.blk_sp, w.blk_slot, w.blk_gap, M, idx, kFillRowsPerWG);
+        APPD_LAUNCH("fill_kernel", s,
+            fill_kernel<kFillCB, WIDEST, false><<<grid, kFillThreads, 0, s>>>(w.pos, w.ek, n,
+                w.blk_sp, w.blk_slot, w.blk_gap, M, idx, kFillRowsPerWG));
     return hipGetLastError();
 }
 

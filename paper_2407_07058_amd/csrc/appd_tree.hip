@@ -743,7 +743,8 @@ static hipError_t launch_fallback(const float* W, int n, PrimOut out, int32_t* c
     const int ch = (n + 1023) / 1024;
 #define APPD_FB(C)                                                                   \
     if (ch <= C) {                                                                   \
-        tree_fallback_kernel<C, WIDEST><<<1, 1024, 0, s>>>(W, n, out, ctrl);         \
+        APPD_LAUNCH("tree_fallback_kernel", s,                                       \
+                    tree_fallback_kernel<C, WIDEST><<<1, 1024, 0, s>>>(W, n, out, ctrl)); \
         return hipGetLastError();                                                    \
     }
     APPD_FB(1)
@@ -763,11 +764,13 @@ static void launch_pass(const float* W, int n, const TreeWs& w, hipStream_t s) {
     const int blocks = (n + kPassThreads / kWave - 1) / (kPassThreads / kWave);
     const bool vec = (n % 4 == 0) && (((uintptr_t)W & 15u) == 0);
     if (vec)
-        tree_pass_kernel<WIDEST, FILTER, true><<<blocks, kPassThreads, 0, s>>>(
-            W, n, w.comp, w.lptr, w.lists, w.ctrl);
+        APPD_LAUNCH("tree_pass_kernel", s,
+            tree_pass_kernel<WIDEST, FILTER, true><<<blocks, kPassThreads, 0, s>>>(W, n, w.comp,
+                w.lptr, w.lists, w.ctrl));
     else
-        tree_pass_kernel<WIDEST, FILTER, false><<<blocks, kPassThreads, 0, s>>>(
-            W, n, w.comp, w.lptr, w.lists, w.ctrl);
+        APPD_LAUNCH("tree_pass_kernel", s,
+            tree_pass_kernel<WIDEST, FILTER, false><<<blocks, kPassThreads, 0, s>>>(W, n, w.comp,
+                w.lptr, w.lists, w.ctrl));
 }
 
 template <bool WIDEST>
@@ -778,7 +781,8 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
     hipError_t e;
 #define APPD_CHK()                                     \
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    tree_init_kernel<<<max(nb, 1), 256, 0, s>>>(n, w.comp, w.best, w.lb, w.ctrl);
+    APPD_LAUNCH("tree_init_kernel", s,
+        tree_init_kernel<<<max(nb, 1), 256, 0, s>>>(n, w.comp, w.best, w.lb, w.ctrl));
     APPD_CHK();
     const bool lds = n <= kMaxLdsN;
     const size_t vbytes = lds ? 4 * (size_t)n : 0;
@@ -798,37 +802,48 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
         else launch_pass<WIDEST, true>(W, n, w, s);
         APPD_CHK();
         if (lds)
-            tree_rounds_kernel<true, WIDEST><<<1, kRoundThreads, round_lds, s>>>(ra);
+            APPD_LAUNCH("tree_rounds_kernel", s,
+                tree_rounds_kernel<true, WIDEST><<<1, kRoundThreads, round_lds, s>>>(ra));
         else
-            tree_rounds_kernel<false, WIDEST><<<1, kRoundThreads, round_lds, s>>>(ra);
+            APPD_LAUNCH("tree_rounds_kernel", s,
+                tree_rounds_kernel<false, WIDEST><<<1, kRoundThreads, round_lds, s>>>(ra));
         APPD_CHK();
     }
     e = launch_fallback<WIDEST>(W, n, out, w.ctrl, s);
     if (e != hipSuccess) return e;
-    tree_keyup_kernel<WIDEST><<<nb, 256, 0, s>>>(W, n, w.par, w.keyup, w.link, w.size,
-                                                 w.gcount, w.ctrl);
+    APPD_LAUNCH("tree_keyup_kernel", s,
+        tree_keyup_kernel<WIDEST><<<nb, 256, 0, s>>>(W, n, w.par, w.keyup, w.link, w.size, w.gcount,
+            w.ctrl));
     APPD_CHK();
-    tree_link_kernel<<<nb, 256, 0, s>>>(n, w.keyup, w.link, w.ctrl);
+    APPD_LAUNCH("tree_link_kernel", s,
+        tree_link_kernel<<<nb, 256, 0, s>>>(n, w.keyup, w.link, w.ctrl));
     APPD_CHK();
-    tree_sizes_kernel<<<nb, 256, 0, s>>>(n, w.link, w.size, w.gcount, w.ctrl);
+    APPD_LAUNCH("tree_sizes_kernel", s,
+        tree_sizes_kernel<<<nb, 256, 0, s>>>(n, w.link, w.size, w.gcount, w.ctrl));
     APPD_CHK();
-    tree_scan_kernel<<<1, kRoundThreads, 0, s>>>(n, w.gcount, w.gstart, w.gfill, w.tstart,
-                                                 w.ctrl);
+    APPD_LAUNCH("tree_scan_kernel", s,
+        tree_scan_kernel<<<1, kRoundThreads, 0, s>>>(n, w.gcount, w.gstart, w.gfill, w.tstart,
+            w.ctrl));
     APPD_CHK();
-    tree_group_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.gfill, w.grouped, w.rank,
-                                         w.ctrl);
+    APPD_LAUNCH("tree_group_kernel", s,
+        tree_group_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.gfill, w.grouped, w.rank,
+            w.ctrl));
     APPD_CHK();
-    tree_rank_kernel<<<1024, kRankTile, 0, s>>>(n, w.gcount, w.gstart, w.tstart, w.grouped,
-                                                w.keyup, w.rank, w.ctrl);
+    APPD_LAUNCH("tree_rank_kernel", s,
+        tree_rank_kernel<<<1024, kRankTile, 0, s>>>(n, w.gcount, w.gstart, w.tstart, w.grouped,
+            w.keyup, w.rank, w.ctrl));
     APPD_CHK();
-    tree_place_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.rank, w.size, w.sorted_size,
-                                         w.sorted_grp, w.ctrl);
+    APPD_LAUNCH("tree_place_kernel", s,
+        tree_place_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.rank, w.size, w.sorted_size,
+            w.sorted_grp, w.ctrl));
     APPD_CHK();
-    tree_segscan_kernel<<<1, kRoundThreads, 0, s>>>(n, w.sorted_size, w.sorted_grp,
-                                                    w.sorted_pre, w.ctrl);
+    APPD_LAUNCH("tree_segscan_kernel", s,
+        tree_segscan_kernel<<<1, kRoundThreads, 0, s>>>(n, w.sorted_size, w.sorted_grp,
+            w.sorted_pre, w.ctrl));
     APPD_CHK();
-    tree_pos_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.rank, w.sorted_pre, w.keyup, w.par,
-                                       out, w.ctrl);
+    APPD_LAUNCH("tree_pos_kernel", s,
+        tree_pos_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.rank, w.sorted_pre, w.keyup,
+            w.par, out, w.ctrl));
     APPD_CHK();
 #undef APPD_CHK
     return hipSuccess;

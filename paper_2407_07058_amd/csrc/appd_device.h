@@ -72,37 +72,89 @@ __device__ __forceinline__ uint64_t shfl_down_u64(uint64_t x, int d) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// All lanes receive the wave-wide minimum.
+// Lane `src` (wave-uniform) of x, to every lane, without going through LDS.
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t x, int src) {
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)x, src);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Lane l receives lane l-1 of x within each row of 16 lanes (DPP row_shr:1);
+// the first lane of a row keeps its own value.
+__device__ __forceinline__ uint64_t row_shr1_u64(uint64_t x) {
+    const int lo = (int)(uint32_t)x, hi = (int)(uint32_t)(x >> 32);
+    const uint32_t rlo = __builtin_amdgcn_update_dpp(lo, lo, 0x111, 0xf, 0xf, false);
+    const uint32_t rhi = __builtin_amdgcn_update_dpp(hi, hi, 0x111, 0xf, 0xf, false);
+    return ((uint64_t)rhi << 32) | rlo;
+}
+
+// ---- cross-lane operations on DPP (data-parallel primitives: lane moves
+// inside the VALU, no LDS round trip) and readlane.
+// dpp_u64<CTRL>: DPP move of x with `fill` where the source lane is outside
+// the row.  row_shr:k (0x110 + k): lane l takes lane l-k of its row of 16;
+// row_shl:k (0x100 + k): lane l takes lane l+k.
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t x, uint64_t fill) {
+    const uint32_t lo = __builtin_amdgcn_update_dpp((int)(uint32_t)fill, (int)(uint32_t)x, CTRL,
+                                                    0xf, 0xf, false);
+    const uint32_t hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(fill >> 32),
+                                                    (int)(uint32_t)(x >> 32), CTRL, 0xf, 0xf, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// All lanes receive the wave-wide minimum: running minima inside each row of
+// 16 lanes (shifts 1, 2, 4, 8), then the four row results by readlane.
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
-#pragma unroll
-    for (int m = 1; m < kWave; m <<= 1) x = umin64(x, shfl_xor_u64(x, m));
-    return x;
+    constexpr uint64_t I = ~0ull;
+    x = umin64(x, dpp_u64<0x111>(x, I));
+    x = umin64(x, dpp_u64<0x112>(x, I));
+    x = umin64(x, dpp_u64<0x114>(x, I));
+    x = umin64(x, dpp_u64<0x118>(x, I));
+    return umin64(umin64(readlane_u64(x, 15), readlane_u64(x, 31)),
+                  umin64(readlane_u64(x, 47), readlane_u64(x, 63)));
 }
 
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
-#pragma unroll
-    for (int m = 1; m < kWave; m <<= 1) x = umax64(x, shfl_xor_u64(x, m));
-    return x;
+    x = umax64(x, dpp_u64<0x111>(x, 0));
+    x = umax64(x, dpp_u64<0x112>(x, 0));
+    x = umax64(x, dpp_u64<0x114>(x, 0));
+    x = umax64(x, dpp_u64<0x118>(x, 0));
+    return umax64(umax64(readlane_u64(x, 15), readlane_u64(x, 31)),
+                  umax64(readlane_u64(x, 47), readlane_u64(x, 63)));
 }
 
-// Inclusive running max over lanes 0..lane.
-__device__ __forceinline__ uint64_t wave_incl_max_up(uint64_t x, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint64_t y = shfl_up_u64(x, d);
-        if (lane >= d) x = umax64(x, y);
-    }
-    return x;
+// Exclusive running max over lanes 0..lane-1 (0 for lane 0).
+__device__ __forceinline__ uint64_t wave_excl_max_up(uint64_t x, int lane) {
+    x = umax64(x, dpp_u64<0x111>(x, 0));
+    x = umax64(x, dpp_u64<0x112>(x, 0));
+    x = umax64(x, dpp_u64<0x114>(x, 0));
+    x = umax64(x, dpp_u64<0x118>(x, 0));  // inclusive within the row
+    const uint64_t r0 = readlane_u64(x, 15), r1 = readlane_u64(x, 31),
+                   r2 = readlane_u64(x, 47);
+    const int row = lane >> 4;
+    const uint64_t carry = row == 0 ? 0ull
+                           : row == 1 ? r0
+                           : row == 2 ? umax64(r0, r1)
+                                      : umax64(umax64(r0, r1), r2);
+    const uint64_t prev = dpp_u64<0x111>(x, 0);  // lane l-1 of the row
+    return (lane & 15) == 0 ? carry : umax64(prev, carry);
 }
 
-// Inclusive running max over lanes lane..63.
-__device__ __forceinline__ uint64_t wave_incl_max_down(uint64_t x, int lane) {
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint64_t y = shfl_down_u64(x, d);
-        if (lane + d < kWave) x = umax64(x, y);
-    }
-    return x;
+// Exclusive running max over lanes lane+1..63 (0 for lane 63).
+__device__ __forceinline__ uint64_t wave_excl_max_down(uint64_t x, int lane) {
+    x = umax64(x, dpp_u64<0x101>(x, 0));
+    x = umax64(x, dpp_u64<0x102>(x, 0));
+    x = umax64(x, dpp_u64<0x104>(x, 0));
+    x = umax64(x, dpp_u64<0x108>(x, 0));  // inclusive within the row, downwards
+    const uint64_t h1 = readlane_u64(x, 16), h2 = readlane_u64(x, 32),
+                   h3 = readlane_u64(x, 48);
+    const int row = lane >> 4;
+    const uint64_t carry = row == 3 ? 0ull
+                           : row == 2 ? h3
+                           : row == 1 ? umax64(h2, h3)
+                                      : umax64(umax64(h1, h2), h3);
+    const uint64_t next = dpp_u64<0x101>(x, 0);  // lane l+1 of the row
+    return (lane & 15) == 15 ? carry : umax64(next, carry);
 }
 
 // Orders LDS traffic of one wave: writes before the fence are visible to reads

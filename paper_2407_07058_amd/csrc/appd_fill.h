@@ -154,12 +154,8 @@ __device__ __forceinline__ void fill_rows_block(const int32_t* __restrict__ pos,
             if (k < ks) loc[q] = run;
         }
         const uint64_t dn_tot = run;
-        uint64_t up_in = wave_incl_max_up(up_tot, lane);
-        up_in = shfl_up_u64(up_in, 1);
-        if (lane == 0) up_in = 0;
-        uint64_t dn_in = wave_incl_max_down(dn_tot, lane);
-        dn_in = shfl_down_u64(dn_in, 1);
-        if (lane == kWave - 1) dn_in = 0;
+        const uint64_t up_in = wave_excl_max_up(up_tot, lane);
+        const uint64_t dn_in = wave_excl_max_down(dn_tot, lane);
 #pragma unroll
         for (int q = 0; q < S; ++q) {
             const int k = k0 + q;

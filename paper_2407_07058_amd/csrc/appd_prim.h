@@ -12,7 +12,7 @@
 // during the update.  A visited vertex holds NaN, which no comparison selects.
 //
 // Each step: the thread's best key (packed 64-bit, see appd_device.h) is
-// reduced across the wave with shuffles and across waves through LDS (one
+// reduced across the wave with DPP moves and across waves through LDS (one
 // barrier per step, double-buffered slots); the winner p is recorded; row p is
 // streamed and the keys updated.  Only the thread that owned p rescans its
 // vertices; the others fold the best improved vertex into their running best.
@@ -84,7 +84,7 @@ __device__ __forceinline__ void prim_run(const float* __restrict__ W, int n, Pri
         const uint64_t wk = wave_min_u64(bkey);
         const uint64_t bal = __ballot(bkey == wk);
         const int src = __ffsll((unsigned long long)bal) - 1;
-        const int32_t wv = __shfl(bv, src);
+        const int32_t wv = __builtin_amdgcn_readlane(bv, src);
         const int slot = (k & 1) * NW;
         if (lane == 0) {
             red_key[slot + wid] = wk;

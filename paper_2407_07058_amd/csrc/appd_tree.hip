@@ -43,6 +43,7 @@ constexpr int kMaxLdsN = 32768;    // comp + parent as 16-bit values in LDS
 constexpr int kLdsBytes = 150 * 1024;  // dynamic LDS the rounds kernel may take
 constexpr int kTableBytes = 28;        // per-component table entry
 constexpr uint64_t kNone = ~0ull;
+constexpr uint16_t kNoId = 0xffff;  // end of a short list (n < 65535 always)
 
 // control block (int32 words); word 32 holds the number of rank tiles
 enum { C_DONE = 0, C_NCOMP, C_NEED_PASS, C_FALLBACK, C_ROUNDS, C_ORDERED, C_WORDS };
@@ -78,17 +79,26 @@ __global__ void tree_init_kernel(int n, int32_t* comp, uint64_t* best, uint64_t*
 
 // ---------------------------------------------------------------- pass
 // One wave per row.  Lanes 0..K-1 hold the row's K smallest entries seen so
-// far, in ascending order; tau is the K-th.  An element is offered only when it
-// beats tau, so after the first few columns almost every element costs one
-// compare: a candidate is broadcast, its rank among the list (a ballot) gives
-// its slot, the lanes above shift up by one.
+// far, in ascending order; tau is the K-th.  The row is read in blocks of
+// kPassElems columns per lane.  Before a block is offered, its threshold is
+// set to the K-th smallest of the 64 lane minima (a bitwise search over the
+// ord32 values with ballots): at least K eligible entries of the block lie at
+// or below it, so nothing above it can enter the list.  Groups of four entries
+// whose minimum lies above min(threshold, tau) cost one compare; an entry that
+// passes is broadcast, its rank among the list (a ballot) gives its slot, and
+// the lanes above shift up by one.
+// All comparisons are made on s = w (minimax) or s = -w (widest); ties at the
+// threshold are offered and ordered by the full key.
 // VEC: rows are 16-byte aligned (n % 4 == 0), each lane reads 4 columns at once.
+constexpr int kPassElems = 32;
+
 template <bool WIDEST, bool FILTER, bool VEC>
 __global__ __launch_bounds__(kPassThreads) void tree_pass_kernel(const float* __restrict__ W,
                                                                  int n,
                                                                  const int32_t* __restrict__ comp,
                                                                  int32_t* __restrict__ lptr,
                                                                  uint64_t* __restrict__ lists,
+                                                                 uint16_t* __restrict__ lids,
                                                                  const int32_t* __restrict__ ctrl) {
     if (ctrl[C_DONE]) return;
     const int lane = threadIdx.x & (kWave - 1);
@@ -96,74 +106,93 @@ __global__ __launch_bounds__(kPassThreads) void tree_pass_kernel(const float* __
     if (u >= n) return;  // no barrier in this kernel
     const float* row = W + (size_t)u * (size_t)n;
     const int cu = FILTER ? comp[u] : u;
-    uint64_t mine = kNone;  // this lane's slot of the sorted list (lanes < K)
-    uint64_t tau = kNone;   // the K-th smallest so far (wave-uniform)
-    auto offer = [&](float w, int v, int cv) {
-        const bool skip = FILTER ? (cv == cu) : (v == u);
-        const uint64_t e =
-            skip ? kNone : (((uint64_t)ord32(WIDEST ? -w : w) << 32) | (uint32_t)v);
+    uint64_t mine = kNone;    // this lane's slot of the sorted list (lanes < K)
+    uint64_t tau = kNone;     // the K-th smallest so far (wave-uniform)
+    float tau_s = INFINITY;   // its s value (+inf while the list is not full)
+    auto offer = [&](float sv, int v, bool skip) {
+        const uint64_t e = skip ? kNone : (((uint64_t)ord32(sv) << 32) | (uint32_t)v);
         uint64_t bal = __ballot(e < tau);
         while (bal) {
             const int src = __ffsll((unsigned long long)bal) - 1;
             bal &= bal - 1;
-            const uint64_t x = shfl_u64(e, src);
+            const uint64_t x = readlane_u64(e, src);
             if (x < tau) {
                 const int pos = __popcll(__ballot(lane < kK && mine < x));
-                const uint64_t below = shfl_up_u64(mine, 1);
+                const uint64_t below = row_shr1_u64(mine);  // the list is lanes 0..15
                 if (lane < kK) mine = lane > pos ? below : (lane == pos ? x : mine);
-                tau = shfl_u64(mine, kK - 1);
+                tau = readlane_u64(mine, kK - 1);
             }
         }
+        tau_s = tau == kNone ? INFINITY : ord32_inv((uint32_t)(tau >> 32));
     };
-    if (VEC) {
-        constexpr int U = 4;
-        // the trip count must be the same for every lane (offer() is wave-wide)
-        for (int b0 = 0; b0 < n; b0 += kWave * 4 * U) {
-            const int base = b0 + lane * 4;
-            float4 x[U];
-            int4 c[U];
+    constexpr int E = kPassElems;
+    constexpr int STEP = kWave * E;
+    // the trip counts are the same for every lane (offer() is wave-wide)
+    for (int b0 = 0; b0 < n; b0 += STEP) {
+        float sv[E];
+        int col[E];
+        bool skip[E];
+        if (VEC) {
 #pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const int v = base + j * kWave * 4;
-                if (v < n) {
-                    x[j] = *(const float4*)(row + v);
-                    if (FILTER) c[j] = *(const int4*)(comp + v);
-                } else {
-                    x[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    c[j] = make_int4(cu, cu, cu, cu);
+            for (int j = 0; j < E / 4; ++j) {
+                const int c0 = b0 + j * (kWave * 4) + lane * 4;
+                float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+                int4 cv = make_int4(cu, cu, cu, cu);
+                if (c0 < n) {
+                    x = *(const float4*)(row + c0);
+                    if (FILTER) cv = *(const int4*)(comp + c0);
+                }
+                const float xs[4] = {x.x, x.y, x.z, x.w};
+                const int cs[4] = {cv.x, cv.y, cv.z, cv.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = 4 * j + q;
+                    col[e] = c0 + q;
+                    sv[e] = WIDEST ? -xs[q] : xs[q];
+                    skip[e] = c0 >= n || (FILTER ? cs[q] == cu : c0 + q == u);
                 }
             }
+        } else {
 #pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const int v = base + j * kWave * 4;
-                // out-of-range columns (v >= n) are offered as skipped entries
-                const bool in = v < n;
-                offer(x[j].x, in ? v : u, FILTER ? c[j].x : 0);
-                offer(x[j].y, in ? v + 1 : u, FILTER ? c[j].y : 0);
-                offer(x[j].z, in ? v + 2 : u, FILTER ? c[j].z : 0);
-                offer(x[j].w, in ? v + 3 : u, FILTER ? c[j].w : 0);
+            for (int e = 0; e < E; ++e) {
+                const int c = b0 + e * kWave + lane;
+                const bool in = c < n;
+                const float x = in ? row[c] : 0.0f;
+                const int cv = (FILTER && in) ? comp[c] : cu;
+                col[e] = c;
+                sv[e] = WIDEST ? -x : x;
+                skip[e] = !in || (FILTER ? cv == cu : c == u);
             }
         }
-    } else {
-        constexpr int U = 8;
-        for (int b0 = 0; b0 < n; b0 += kWave * U) {
-            const int base = b0 + lane;
-            float x[U];
-            int c[U];
+        // K-th smallest lane minimum of this block
+        float lm = INFINITY;
 #pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const int v = base + j * kWave;
-                x[j] = v < n ? row[v] : 0.0f;
-                c[j] = (FILTER && v < n) ? comp[v] : cu;
-            }
+        for (int e = 0; e < E; ++e) lm = fminf(lm, skip[e] ? INFINITY : sv[e]);
+        const uint32_t km = ord32(lm);
+        uint32_t res = 0;
+        for (int b = 31; b >= 0; --b) {
+            const uint32_t c = res | (1u << b);
+            if (__popcll(__ballot(km < c)) < kK) res = c;
+        }
+        const float tblk = ord32_inv(res);
 #pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const int v = base + j * kWave;
-                offer(x[j], v < n ? v : u, FILTER ? c[j] : 0);
+        for (int g = 0; g < E / 4; ++g) {
+            const float thr = fminf(tblk, tau_s);
+            float m4 = INFINITY;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) m4 = fminf(m4, skip[4 * g + q] ? INFINITY : sv[4 * g + q]);
+            if (!__ballot(m4 <= thr)) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = 4 * g + q;
+                offer(sv[e], col[e], skip[e] || !(sv[e] <= thr));
             }
         }
     }
-    if (lane < kK) lists[(size_t)u * kK + lane] = mine;
+    if (lane < kK) {
+        lists[(size_t)u * kK + lane] = mine;
+        lids[(size_t)u * kK + lane] = mine == kNone ? kNoId : (uint16_t)(uint32_t)mine;
+    }
     if (lane == 0) lptr[u] = 0;
 }
 
@@ -176,6 +205,7 @@ struct RoundArgs {
     uint64_t* lb;
     int32_t* lptr;
     const uint64_t* lists;
+    const uint16_t* lids;  // vertex ids of the list entries, 32 bytes per vertex
     int32_t* hook;
     int32_t* hx;  // hooking endpoint inside the component
     int32_t* hy;  // endpoint outside
@@ -184,18 +214,32 @@ struct RoundArgs {
     int cm;  // capacity of the per-component LDS tables
 };
 
-// Block-wide exclusive scan (one workgroup of kRoundThreads threads).
+// Block-wide exclusive scan (one workgroup of kRoundThreads threads): wave
+// scans by shuffles, then one scan over the 16 wave totals.  s: kRoundThreads ints.
 __device__ __forceinline__ int block_excl_scan(int x, int* s) {
+    constexpr int NW = kRoundThreads / kWave;
     const int t = threadIdx.x;
-    s[t] = x;
-    __syncthreads();
-    for (int d = 1; d < kRoundThreads; d <<= 1) {
-        const int y = t >= d ? s[t - d] : 0;
-        __syncthreads();
-        s[t] += y;
-        __syncthreads();
+    const int lane = t & (kWave - 1), wid = t / kWave;
+    int incl = x;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
     }
-    const int r = s[t] - x;
+    if (lane == kWave - 1) s[wid] = incl;
+    __syncthreads();
+    if (t < kWave) {
+        const int v = t < NW ? s[t] : 0;
+        int w = v;
+#pragma unroll
+        for (int d = 1; d < NW; d <<= 1) {
+            const int y = __shfl_up(w, d);
+            if (t >= d) w += y;
+        }
+        if (t < NW) s[NW + t] = w - v;
+    }
+    __syncthreads();
+    const int r = s[NW + wid] + incl - x;
     __syncthreads();
     return r;
 }
@@ -243,6 +287,7 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
         if (LDS) v_par[v] = p < 0 ? NIL : (uint16_t)p;
         else a.par[v] = p;
     };
+    if (t == 0) s_flag[3] = 0;  // pending walks of the current round
     int C = ctrl[C_NCOMP];
     bool small = C <= cm;
     auto get_best = [&](int d) { return small ? t_best[d] : ld_l2(&a.best[d]); };
@@ -272,72 +317,199 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
     };
     // the rooted forest built so far (first call: every vertex its own root)
     const bool first = ctrl[C_ROUNDS] == 0;
-    for (int v = t; v < n; v += kRoundThreads) {
-        if (LDS) {
-            setc(v, first ? v : a.comp[v]);
-            setp(v, first ? -1 : a.par[v]);
-        } else if (first) {
-            a.par[v] = -1;
+    if (LDS && first && !ctrl[C_DONE]) {
+        // Round 1, all in LDS.  Every vertex is its own component and its list's
+        // first entry is its cheapest edge, so it hooks along it; the only
+        // cycles are pairs that chose the same edge, whose smaller vertex stays
+        // the root.  parent = hook target for every other vertex.
+        constexpr int kV = 8;
+        for (int base = 0; base < n; base += kV * kRoundThreads) {
+            uint16_t e[kV];
+#pragma unroll
+            for (int i = 0; i < kV; ++i) {
+                const int u = base + i * kRoundThreads + t;
+                e[i] = u < n ? a.lids[(size_t)u * kK] : kNoId;
+            }
+#pragma unroll
+            for (int i = 0; i < kV; ++i) {
+                const int u = base + i * kRoundThreads + t;
+                if (u < n) v_par[u] = e[i] == kNoId ? (uint16_t)u : e[i];
+            }
         }
+        __syncthreads();
+        // roots: vertices hooked to themselves, and the smaller end of a pair
+        uint32_t rootbits = 0;  // bit i: vertex t + i * kRoundThreads (n <= 32 * 1024)
+        for (int i = 0, u = t; u < n; ++i, u += kRoundThreads) {
+            const int h = v_par[u];
+            if (h == u || (v_par[h] == u && u < h)) rootbits |= 1u << i;
+        }
+        __syncthreads();
+        for (int i = 0, u = t; u < n; ++i, u += kRoundThreads) {
+            const bool r = (rootbits >> i) & 1u;
+            v_comp[u] = r ? (uint16_t)u : v_par[u];
+            if (r) v_par[u] = NIL;
+        }
+        __syncthreads();
+        // component = root of the hook forest, by pointer jumping
+        for (int it = 0; it < 64; ++it) {
+            if (t == 0) s_flag[1] = 0;
+            __syncthreads();
+            bool ch = false;
+            for (int u = t; u < n; u += kRoundThreads) {
+                const int c = v_comp[u];
+                const int cc = v_comp[c];
+                if (cc != c) {
+                    v_comp[u] = (uint16_t)cc;
+                    ch = true;
+                }
+            }
+            if (ch) s_flag[1] = 1;
+            __syncthreads();
+            const int again = s_flag[1];
+            __syncthreads();
+            if (!again) break;
+        }
+        // dense numbers: id(root r) = number of roots below r, from a bitmap of
+        // the roots (64 per word) and the exclusive prefix of its word counts
+        uint64_t* bits = s_dyn;  // n/64 words, then n/64 prefix counts
+        int32_t* wpre = (int32_t*)(bits + (n + kWave - 1) / kWave);
+        const int nw = (n + kWave - 1) / kWave;
+        for (int w = t / kWave; w < nw; w += kRoundThreads / kWave) {
+            const int u = w * kWave + lane;
+            const uint64_t m = __ballot(u < n && v_par[u] == NIL);
+            if (lane == 0) bits[w] = m;
+        }
+        __syncthreads();
+        // nw <= 512 < kRoundThreads: one word per thread
+        const int pre = block_excl_scan(t < nw ? __popcll(bits[t]) : 0, s_scan);
+        if (t < nw) wpre[t] = pre;
+        if (t == nw - 1) s_flag[2] = pre + __popcll(bits[t]);
+        __syncthreads();
+        C = s_flag[2];
+        for (int u = t; u < n; u += kRoundThreads) {
+            const int r = v_comp[u];
+            const int w = r / kWave;
+            v_comp[u] = (uint16_t)(wpre[w] + __popcll(bits[w] & ((1ull << (r & (kWave - 1))) - 1)));
+        }
+        __syncthreads();
+        small = C <= cm;
+        if (t == 0) {
+            ctrl[C_ROUNDS] = 1;
+            ctrl[C_NCOMP] = C;
+            if (C == 1) ctrl[C_DONE] = 1;
+        }
+        for (int d = t; d < C; d += kRoundThreads) {
+            if (small) t_best[d] = t_lb[d] = kNone;
+            else a.best[d] = a.lb[d] = kNone;
+        }
+    } else {
+        for (int v = t; v < n; v += kRoundThreads) {
+            if (LDS) {
+                setc(v, first ? v : a.comp[v]);
+                setp(v, first ? -1 : a.par[v]);
+            } else if (first) {
+                a.par[v] = -1;
+            }
+        }
+        if (small)
+            for (int d = t; d < C; d += kRoundThreads) t_best[d] = t_lb[d] = kNone;
     }
-    if (small)
-        for (int d = t; d < C; d += kRoundThreads) t_best[d] = t_lb[d] = kNone;
     __syncthreads();
 
-    constexpr int kChunk = 8;
-    constexpr int kStride = kChunk * kRoundThreads;
-    for (int guard = 0; guard < 64 && !ctrl[C_DONE]; ++guard) {
+    // 1. cheapest outgoing candidate (or lower bound) of every vertex.  Each
+    //    round a vertex examines the rest of the aligned group of four list
+    //    entries that holds its list pointer (one 8-byte load of vertex ids,
+    //    endpoint components from LDS).  The first entry leaving its component
+    //    is its exact cheapest outgoing edge.  If the whole group is internal,
+    //    every outgoing edge of the vertex is larger than the group's last
+    //    entry, whose key becomes a lower bound, and the pointer moves to the
+    //    next group (a vertex still walking its list is "pending"); an
+    //    exhausted list bounds by entry K-1.  Either way one key is read per
+    //    vertex.  A wave whose vertices share one component sends one atomic
+    //    per minimum.
+    constexpr int kW = 8;  // vertices per thread
+    constexpr int kStride = kW * kRoundThreads;
+    for (int guard = 0; guard < 128 && !ctrl[C_DONE]; ++guard) {
         if (t == 0) {
             s_flag[0] = 0;  // components that decided this round
             ctrl[C_ROUNDS] += 1;
         }
-        // 1. cheapest outgoing candidate (or lower bound) of every vertex; a wave
-        //    whose vertices share one component sends one atomic per minimum.
-        //    The list words a vertex usually needs (its current entry, the next
-        //    one and the last) are gathered for kChunk vertices before use.
         for (int base = 0; base < n; base += kStride) {
-            int pp[kChunk];
-            uint64_t e0[kChunk], e1[kChunk], el[kChunk];
+            int pp[kW], p0[kW], cu[kW];
+            uint64_t ids[kW];
 #pragma unroll
-            for (int i = 0; i < kChunk; ++i) {
+            for (int i = 0; i < kW; ++i) {
                 const int u = base + i * kRoundThreads + t;
                 pp[i] = u < n ? a.lptr[u] : kK;
+                p0[i] = pp[i];
             }
 #pragma unroll
-            for (int i = 0; i < kChunk; ++i) {
+            for (int i = 0; i < kW; ++i) {
                 const int u = base + i * kRoundThreads + t;
-                const uint64_t* L = a.lists + (size_t)u * kK;
-                const bool ok = u < n && pp[i] < kK;
-                e0[i] = ok ? L[pp[i]] : kNone;
-                e1[i] = (ok && pp[i] + 1 < kK) ? L[pp[i] + 1] : kNone;
-                el[i] = u < n ? L[kK - 1] : kNone;
+                const int q = pp[i] & ~3;
+                ids[i] = (u < n && pp[i] < kK) ? *(const uint64_t*)(a.lids + (size_t)u * kK + q)
+                                               : ~0ull;
+                cu[i] = u < n ? getc(u) : -1;
             }
+            bool pend[kW], bound[kW];
 #pragma unroll
-            for (int i = 0; i < kChunk; ++i) {
+            for (int i = 0; i < kW; ++i) {
+                const int u = base + i * kRoundThreads + t;
+                pend[i] = false;
+                bound[i] = u < n && pp[i] >= kK;  // exhausted before this round
+                if (u >= n || pp[i] >= kK) continue;
+                const int q = pp[i] & ~3;
+                int found = -1;
+                bool shortl = false;
+#pragma unroll
+                for (int r = 3; r >= 0; --r) {  // the first qualifying entry wins
+                    const uint32_t v = (uint32_t)(ids[i] >> (16 * r)) & 0xffffu;
+                    if (q + r < pp[i]) continue;
+                    if (v == kNoId) {
+                        shortl = true;
+                        found = -1;
+                    } else if (getc((int)v) != cu[i]) {
+                        found = r;
+                        shortl = false;
+                    }
+                }
+                if (found >= 0) {
+                    pp[i] = q + found;
+                } else if (shortl) {
+                    pp[i] = kK;  // nothing beyond a short list: no bound
+                } else {
+                    pp[i] = q + 4;     // whole group internal
+                    bound[i] = true;   // key of entry q+3 bounds the vertex
+                    pend[i] = pp[i] < kK;
+                }
+            }
+            uint64_t ent[kW];
+#pragma unroll
+            for (int i = 0; i < kW; ++i) {
+                const int u = base + i * kRoundThreads + t;
+                int slot = -1;
+                if (u < n) {
+                    if (bound[i]) slot = (pp[i] >= kK ? kK : pp[i]) - 1;
+                    else if (pp[i] < kK) slot = pp[i];
+                }
+                ent[i] = slot >= 0 ? a.lists[(size_t)u * kK + slot] : kNone;
+            }
+            int npend = 0;
+#pragma unroll
+            for (int i = 0; i < kW; ++i) {
                 const int u = base + i * kRoundThreads + t;
                 const bool act = u < n;
-                int cu = -1;
                 uint64_t kc = kNone, kb = kNone;
                 if (act) {
-                    const uint64_t* L = a.lists + (size_t)u * kK;
-                    cu = getc(u);
-                    int p = pp[i];
-                    uint64_t ent = e0[i];
-                    if (p < kK && ent != kNone && getc((int)(uint32_t)ent) == cu) {
-                        ++p;
-                        ent = e1[i];
-                        while (p < kK && ent != kNone && getc((int)(uint32_t)ent) == cu) {
-                            ++p;
-                            ent = p < kK ? L[p] : kNone;
-                        }
+                    if (ent[i] != kNone) {
+                        if (bound[i]) kb = edge_key_of(ent[i], u, n);
+                        else kc = edge_key_of(ent[i], u, n);
                     }
-                    if (p < kK && ent == kNone) p = kK;  // short list: nothing beyond it
-                    if (p != pp[i]) a.lptr[u] = p;
-                    if (p < kK) kc = edge_key_of(ent, u, n);
-                    else if (el[i] != kNone) kb = edge_key_of(el[i], u, n);
+                    if (pp[i] != p0[i]) a.lptr[u] = pp[i];
                 }
-                const int c0 = __shfl(cu, 0);
-                const uint64_t same = __ballot(act && cu == c0);
+                npend += __popcll(__ballot(pend[i]));
+                const int c0 = __builtin_amdgcn_readfirstlane(cu[i]);
+                const uint64_t same = __ballot(act && cu[i] == c0);
                 const uint64_t acts = __ballot(act);
                 if (same == acts) {
                     const uint64_t mc = wave_min_u64(kc), mb = wave_min_u64(kb);
@@ -346,10 +518,11 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
                         if (mb != kNone) min_lb(c0, mb);
                     }
                 } else if (act) {
-                    if (kc != kNone) min_best(cu, kc);
-                    if (kb != kNone) min_lb(cu, kb);
+                    if (kc != kNone) min_best(cu[i], kc);
+                    if (kb != kNone) min_lb(cu[i], kb);
                 }
             }
+            if (lane == 0 && npend) atomicAdd(&s_flag[3], npend);
         }
         __syncthreads();
         // 2. decide: a component hooks when its best exact candidate beats every bound
@@ -370,11 +543,19 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
         }
         __syncthreads();
         const int decided = s_flag[0];
+        const int pending = s_flag[3];
+        __syncthreads();  // every thread has read the counters
+        if (t == 0) s_flag[3] = 0;  // ordered before the next round by the barriers below
         if (decided == 0) {
-            // the minima gathered from these lists are stale once the lists are
-            // refreshed: clear them for the next call
-            if (!small)
-                for (int d = t; d < C; d += kRoundThreads) a.best[d] = a.lb[d] = kNone;
+            // minima of this round are stale either way: clear them
+            for (int d = t; d < C; d += kRoundThreads) {
+                if (small) t_best[d] = t_lb[d] = kNone;
+                else a.best[d] = a.lb[d] = kNone;
+            }
+            if (pending > 0) {  // lists still being walked: another round
+                __syncthreads();
+                continue;
+            }
             if (t == 0) ctrl[C_NEED_PASS] = 1;
             break;
         }
@@ -699,6 +880,7 @@ __global__ __launch_bounds__(1024) void tree_fallback_kernel(const float* __rest
 // ---------------------------------------------------------------- host side
 struct TreeWs {
     uint64_t* lists;
+    uint16_t* lids;
     int32_t *comp, *lptr, *hook, *hx, *hy, *par, *link, *size, *gcount, *gstart, *gfill;
     int32_t *tstart, *grouped, *rank, *sorted_size, *sorted_grp, *sorted_pre;
     uint64_t *best, *lb, *keyup;
@@ -718,6 +900,7 @@ static TreeWs carve_tree(void* ws, int n) {
     };
     TreeWs w;
     w.lists = (uint64_t*)take(8 * (size_t)n * kK);
+    w.lids = (uint16_t*)take(2 * (size_t)n * kK);
     int32_t** ints[11] = {&w.comp, &w.lptr, &w.hook, &w.hx, &w.hy, &w.par,
                           &w.link, &w.size, &w.gcount, &w.gstart, &w.gfill};
     for (int i = 0; i < 11; ++i) *ints[i] = (int32_t*)take(4 * (size_t)n);
@@ -766,11 +949,11 @@ static void launch_pass(const float* W, int n, const TreeWs& w, hipStream_t s) {
     if (vec)
         APPD_LAUNCH("tree_pass_kernel", s,
             tree_pass_kernel<WIDEST, FILTER, true><<<blocks, kPassThreads, 0, s>>>(W, n, w.comp,
-                w.lptr, w.lists, w.ctrl));
+                w.lptr, w.lists, w.lids, w.ctrl));
     else
         APPD_LAUNCH("tree_pass_kernel", s,
             tree_pass_kernel<WIDEST, FILTER, false><<<blocks, kPassThreads, 0, s>>>(W, n, w.comp,
-                w.lptr, w.lists, w.ctrl));
+                w.lptr, w.lists, w.lids, w.ctrl));
 }
 
 template <bool WIDEST>
@@ -795,7 +978,7 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)round_lds);
         if (e != hipSuccess) return e;
     }
-    RoundArgs ra{W,      n,    w.comp, w.best, w.lb, w.lptr, w.lists,
+    RoundArgs ra{W,      n,    w.comp, w.best, w.lb, w.lptr, w.lists, w.lids,
                  w.hook, w.hx, w.hy,   w.par,  w.ctrl, cm};
     for (int p = 0; p < kPasses; ++p) {
         if (p == 0) launch_pass<WIDEST, false>(W, n, w, s);

@@ -33,17 +33,28 @@
 
 namespace appd {
 
-// Block prep: one workgroup (256 threads) per column block.
+// Block prep: one workgroup (256 threads) per column block.  The block's
+// columns are sorted by attachment position (bitonic sort in LDS); then the gap
+// maxima are taken in one sweep over ek: position p (sp[k-1] < p <= sp[k])
+// belongs to slot k = the number of sorted positions below p, read off a bitmap
+// of those positions and its per-word prefix counts, and is folded into gap[k]
+// with an LDS atomic max.  ek is read coalesced, once per block.
+// LDS: keys CB words; bits and prefix (n + 31) / 32 words each; gap CB keys.
 template <int CB>
 __device__ __forceinline__ void fill_prep_block(const int32_t* __restrict__ pos,
                                                 const uint64_t* __restrict__ ek, int n, int blk,
                                                 uint16_t* __restrict__ blk_sp,
                                                 uint16_t* __restrict__ blk_slot,
-                                                uint64_t* __restrict__ blk_gap, uint32_t* keys) {
+                                                uint64_t* __restrict__ blk_gap, uint32_t* keys,
+                                                uint32_t* bits, int32_t* wpre, uint64_t* gap) {
     const int j0 = blk * CB;
     const int cnt = min(CB, n - j0);
-    for (int c = threadIdx.x; c < CB; c += blockDim.x)
+    const int nw = (n + 31) / 32;
+    for (int c = threadIdx.x; c < CB; c += blockDim.x) {
         keys[c] = c < cnt ? (((uint32_t)pos[j0 + c] << 16) | (uint32_t)c) : 0xffffffffu;
+        gap[c] = 0;
+    }
+    for (int w = threadIdx.x; w < nw; w += blockDim.x) bits[w] = 0;
     __syncthreads();
     // bitonic sort, ascending
     for (int size = 2; size <= CB; size <<= 1) {
@@ -67,13 +78,38 @@ __device__ __forceinline__ void fill_prep_block(const int32_t* __restrict__ pos,
         const int col = (int)(kk & 0xffffu);
         blk_sp[j0 + k] = (uint16_t)sp;
         blk_slot[j0 + col] = (uint16_t)k;
-        uint64_t g = 0;
-        if (k > 0) {
-            const int lo = (int)(keys[k - 1] >> 16) + 1;
-            for (int s = lo; s <= sp; ++s) g = umax64(g, ek[s]);
-        }
-        blk_gap[j0 + k] = g;
+        atomicOr(&bits[sp >> 5], 1u << (sp & 31));
     }
+    __syncthreads();
+    // exclusive prefix of the word counts (one thread per run of words)
+    const int per = (nw + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int w0 = min(nw, (int)threadIdx.x * per), w1 = min(nw, w0 + per);
+    int c = 0;
+    for (int w = w0; w < w1; ++w) c += __popc(bits[w]);
+    // exclusive scan of the threads' counts (Hillis-Steele in LDS)
+    __shared__ int s_cnt[256];
+    s_cnt[threadIdx.x] = c;
+    __syncthreads();
+    for (int d = 1; d < (int)blockDim.x; d <<= 1) {
+        const int y = (int)threadIdx.x >= d ? s_cnt[threadIdx.x - d] : 0;
+        __syncthreads();
+        s_cnt[threadIdx.x] += y;
+        __syncthreads();
+    }
+    int run = s_cnt[threadIdx.x] - c;
+    for (int w = w0; w < w1; ++w) {
+        wpre[w] = run;
+        run += __popc(bits[w]);
+    }
+    __syncthreads();
+    // one sweep over ek: position p > sp[0] lies in slot k = #{sp < p}
+    const int lo = (int)(keys[0] >> 16) + 1, hi = (int)(keys[cnt - 1] >> 16);
+    for (int p = lo + (int)threadIdx.x; p <= hi; p += blockDim.x) {
+        const int k = wpre[p >> 5] + __popc(bits[p >> 5] & ((1u << (p & 31)) - 1u));
+        atomicMax((unsigned long long*)&gap[k], (unsigned long long)ek[p]);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) blk_gap[j0 + k] = gap[k];
 }
 
 // One column block, rows [r0, r1), waves of the workgroup take rows in turn.

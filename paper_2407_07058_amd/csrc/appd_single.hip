@@ -26,7 +26,10 @@ __global__ __launch_bounds__(kFillThreads) void fill_prep_kernel(const int32_t* 
                                                                  uint16_t* blk_slot,
                                                                  uint64_t* blk_gap) {
     __shared__ uint32_t keys[CB];
-    fill_prep_block<CB>(pos, ek, n, blockIdx.x, blk_sp, blk_slot, blk_gap, keys);
+    __shared__ uint32_t bits[(APPD_MAX_N + 31) / 32];
+    __shared__ int32_t wpre[(APPD_MAX_N + 31) / 32];
+    __shared__ uint64_t gap[CB];
+    fill_prep_block<CB>(pos, ek, n, blockIdx.x, blk_sp, blk_slot, blk_gap, keys, bits, wpre, gap);
 }
 
 template <int CB, bool WIDEST, bool VEC>

@@ -168,13 +168,19 @@ __global__ __launch_bounds__(kPassThreads) void tree_pass_kernel(const float* __
         float lm = INFINITY;
 #pragma unroll
         for (int e = 0; e < E; ++e) lm = fminf(lm, skip[e] ? INFINITY : sv[e]);
-        const uint32_t km = ord32(lm);
-        uint32_t res = 0;
-        for (int b = 31; b >= 0; --b) {
-            const uint32_t c = res | (1u << b);
-            if (__popcll(__ballot(km < c)) < kK) res = c;
+        // (skipped when fewer than K lane minima lie below tau: it could not
+        // improve on tau).  The search runs over the top 16 bits of the ord32
+        // values, which rounds the threshold up: still a valid bound.
+        float tblk = INFINITY;
+        if (__popcll(__ballot(lm < tau_s)) >= kK) {
+            const uint32_t km = ord32(lm) >> 16;
+            uint32_t res = 0;
+            for (int b = 15; b >= 0; --b) {
+                const uint32_t c = res | (1u << b);
+                if (__popcll(__ballot(km < c)) < kK) res = c;
+            }
+            tblk = res == 0xffffu ? INFINITY : ord32_inv((res << 16) | 0xffffu);
         }
-        const float tblk = ord32_inv(res);
 #pragma unroll
         for (int g = 0; g < E / 4; ++g) {
             const float thr = fminf(tblk, tau_s);
@@ -655,7 +661,8 @@ template <bool WIDEST>
 __global__ __launch_bounds__(256) void tree_keyup_kernel(const float* __restrict__ W, int n,
                                                         const int32_t* par, uint64_t* keyup,
                                                         int32_t* link, int32_t* size,
-                                                        int32_t* gcount, const int32_t* ctrl) {
+                                                        int32_t* gcount, int32_t* arrived,
+                                                        const int32_t* ctrl) {
     if (!ctrl[C_ORDERED]) return;
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
@@ -666,6 +673,24 @@ __global__ __launch_bounds__(256) void tree_keyup_kernel(const float* __restrict
     link[v] = p;
     size[v] = 1;
     gcount[v] = 0;
+    arrived[v] = 0;
+}
+
+// arr[target] += 1 for every active lane.  Lanes aiming at vertex 0 (the
+// largest sibling group by far) and lanes sharing the first remaining lane's
+// target are folded into one atomic each.
+__device__ __forceinline__ void add_folded(int32_t* arr, int target) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t m0 = __ballot(target == 0);
+    if (m0 && lane == (int)(__ffsll((unsigned long long)m0) - 1)) atomicAdd(&arr[0], __popcll(m0));
+    if (target == 0) return;
+    const int lead = __builtin_amdgcn_readfirstlane(target);
+    const uint64_t m = __ballot(target == lead);
+    if (target == lead) {
+        if (lane == (int)(__ffsll((unsigned long long)m) - 1)) atomicAdd(&arr[lead], __popcll(m));
+    } else {
+        atomicAdd(&arr[target], 1);
+    }
 }
 
 // link(v): jump over ancestors whose edge is smaller than e(v).  Any value a
@@ -674,7 +699,8 @@ __global__ __launch_bounds__(256) void tree_keyup_kernel(const float* __restrict
 // it publishes its own progress as it goes.  Every jump moves up the tree, so
 // each thread ends.
 __global__ __launch_bounds__(256) void tree_link_kernel(int n, const uint64_t* keyup,
-                                                       int32_t* link, const int32_t* ctrl) {
+                                                       int32_t* link, int32_t* gcount,
+                                                       const int32_t* ctrl) {
     if (!ctrl[C_ORDERED]) return;
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v == 0 || v >= n) return;
@@ -684,48 +710,130 @@ __global__ __launch_bounds__(256) void tree_link_kernel(int n, const uint64_t* k
         c = link[c];
         link[v] = c;
     }
+    add_folded(gcount, c);  // sibling-group sizes
 }
 
-// link-subtree sizes and sibling-group sizes
+// Link-subtree sizes, bottom-up: a thread starts at every leaf of the link
+// tree and adds its subtree size to its link parent; the child that arrives
+// last at a vertex (its arrival completes the count) carries that vertex's
+// now final size further up.  Every add is released by the arrival that
+// follows it and acquired by the last arrival, so the size it reads is final.
+// The root's size (n) is never needed.
 __global__ __launch_bounds__(256) void tree_sizes_kernel(int n, const int32_t* link,
-                                                        int32_t* size, int32_t* gcount,
-                                                        const int32_t* ctrl) {
+                                                        int32_t* size, const int32_t* gcount,
+                                                        int32_t* arrived, const int32_t* ctrl) {
     if (!ctrl[C_ORDERED]) return;
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v == 0 || v >= n) return;
-    const int g = link[v];
-    atomicAdd(&gcount[g], 1);
-    for (int x = g; x > 0; x = link[x]) atomicAdd(&size[x], 1);
+    if (v == 0 || v >= n || gcount[v] != 0) return;
+    int x = v, sx = 1;
+    for (int guard = 0; guard < n; ++guard) {
+        const int p = link[x];
+        if (p <= 0) break;
+        __hip_atomic_fetch_add(&size[p], sx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int old =
+            __hip_atomic_fetch_add(&arrived[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1 != gcount[p]) break;
+        sx = __hip_atomic_load(&size[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = p;
+    }
 }
 
-// One workgroup: group starts and rank-tile starts (exclusive scans over n).
-__global__ __launch_bounds__(kRoundThreads) void tree_scan_kernel(int n, const int32_t* gcount,
-                                                                 int32_t* gstart, int32_t* gfill,
-                                                                 int32_t* tstart, int32_t* ctrl) {
-    __shared__ int s_scan[kRoundThreads];
+// Exclusive scans over the n vertices in two grid launches: each block of
+// kScanThreads threads owns kScanBlock consecutive elements (8 per thread);
+// the first launch writes the block totals, the second adds the totals of the
+// blocks before it and scans its own elements.
+constexpr int kScanThreads = 256;
+constexpr int kScanBlock = 8 * kScanThreads;
+
+// Exclusive scan over the 256 threads of a block; *total gets the sum.
+__device__ __forceinline__ int block256_excl_scan(int x, int* s, int* total) {
+    const int t = threadIdx.x, lane = t & (kWave - 1), wid = t / kWave;
+    int incl = x;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
+    }
+    if (lane == kWave - 1) s[wid] = incl;
+    __syncthreads();
+    int before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / kWave; ++w) {
+        const int v = s[w];
+        before += w < wid ? v : 0;
+        all += v;
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - x;
+}
+
+// group sizes and rank-tile counts per block
+__global__ __launch_bounds__(kScanThreads) void tree_scanpart_kernel(int n, const int32_t* gcount,
+                                                                    int32_t* bsum,
+                                                                    const int32_t* ctrl) {
+    __shared__ int s_a[8], s_b[8];
     if (!ctrl[C_ORDERED]) return;
-    const int t = threadIdx.x;
-    const int per = (n + kRoundThreads - 1) / kRoundThreads;
-    const int b0 = min(n, t * per), b1 = min(n, b0 + per);
+    const int b0 = blockIdx.x * kScanBlock + threadIdx.x * 8;
     int s = 0, ts = 0;
-    for (int i = b0; i < b1; ++i) {
-        const int m = gcount[i];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int m = b0 + j < n ? gcount[b0 + j] : 0;
         const int nt = (m + kRankTile - 1) / kRankTile;
         s += m;
         ts += m > 1 ? nt * nt : 0;
     }
-    int run = block_excl_scan(s, s_scan);
-    int trun = block_excl_scan(ts, s_scan);
-    for (int i = b0; i < b1; ++i) {
-        const int m = gcount[i];
-        const int nt = (m + kRankTile - 1) / kRankTile;
-        gstart[i] = run;
-        gfill[i] = 0;
-        tstart[i] = trun;
-        run += m;
-        trun += m > 1 ? nt * nt : 0;
+    int ta, tb;
+    (void)block256_excl_scan(s, s_a, &ta);
+    (void)block256_excl_scan(ts, s_b, &tb);
+    if (threadIdx.x == 0) {
+        bsum[2 * blockIdx.x] = ta;
+        bsum[2 * blockIdx.x + 1] = tb;
     }
-    if (t == kRoundThreads - 1) ctrl[C_TILES] = trun;
+}
+
+// group starts, cleared fill counters, rank-tile starts; the last block
+// records the number of rank tiles
+__global__ __launch_bounds__(kScanThreads) void tree_scan_kernel(int n, const int32_t* gcount,
+                                                                int32_t* gstart, int32_t* gfill,
+                                                                int32_t* tstart,
+                                                                const int32_t* bsum,
+                                                                int32_t* owner, int32_t* ctrl) {
+    __shared__ int s_a[8], s_b[8];
+    if (!ctrl[C_ORDERED]) return;
+    int run = 0, trun = 0;
+    for (int b = 0; b < (int)blockIdx.x; ++b) {
+        run += bsum[2 * b];
+        trun += bsum[2 * b + 1];
+    }
+    const int b0 = blockIdx.x * kScanBlock + threadIdx.x * 8;
+    int m[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) m[j] = b0 + j < n ? gcount[b0 + j] : 0;
+    int s = 0, ts = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int nt = (m[j] + kRankTile - 1) / kRankTile;
+        s += m[j];
+        ts += m[j] > 1 ? nt * nt : 0;
+    }
+    int ta, tb;
+    int r = run + block256_excl_scan(s, s_a, &ta);
+    int tr = trun + block256_excl_scan(ts, s_b, &tb);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        if (b0 + j < n) {
+            const int nt = (m[j] + kRankTile - 1) / kRankTile;
+            gstart[b0 + j] = r;
+            gfill[b0 + j] = 0;
+            tstart[b0 + j] = tr;
+            r += m[j];
+            if (m[j] > 1)  // rank tiles of this group belong to it
+                for (int k = 0; k < nt * nt; ++k) owner[tr + k] = b0 + j;
+            tr += m[j] > 1 ? nt * nt : 0;
+        }
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) ctrl[C_TILES] = trun + tb;
 }
 
 __global__ __launch_bounds__(256) void tree_group_kernel(int n, const int32_t* link,
@@ -736,7 +844,29 @@ __global__ __launch_bounds__(256) void tree_group_kernel(int n, const int32_t* l
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v == 0 || v >= n) return;
     const int g = link[v];
-    grouped[gstart[g] + atomicAdd(&gfill[g], 1)] = v;
+    // lanes of the same group as the first active lane, or of vertex 0's group,
+    // take consecutive slots from one atomic
+    const int lane = threadIdx.x & (kWave - 1);
+    const int lead = __builtin_amdgcn_readfirstlane(g);
+    const uint64_t ml = __ballot(g == lead);
+    const uint64_t m0 = lead == 0 ? 0ull : __ballot(g == 0);
+    int slot = 0;
+    if (m0) {
+        const int first = __ffsll((unsigned long long)m0) - 1;
+        int b = 0;
+        if (lane == first) b = atomicAdd(&gfill[0], __popcll(m0));
+        b = __builtin_amdgcn_readlane(b, first);
+        if (g == 0) slot = b + __popcll(m0 & ((1ull << lane) - 1));
+    }
+    {
+        const int first = __ffsll((unsigned long long)ml) - 1;
+        int b = 0;
+        if (lane == first) b = atomicAdd(&gfill[lead], __popcll(ml));
+        b = __builtin_amdgcn_readlane(b, first);
+        if (g == lead) slot = b + __popcll(ml & ((1ull << lane) - 1));
+    }
+    if (g != lead && g != 0) slot = atomicAdd(&gfill[g], 1);
+    grouped[gstart[g] + slot] = v;
     rank[v] = 0;
 }
 
@@ -745,6 +875,7 @@ __global__ __launch_bounds__(256) void tree_group_kernel(int n, const int32_t* l
 __global__ __launch_bounds__(kRankTile) void tree_rank_kernel(int n, const int32_t* gcount,
                                                              const int32_t* gstart,
                                                              const int32_t* tstart,
+                                                             const int32_t* owner,
                                                              const int32_t* grouped,
                                                              const uint64_t* keyup, int32_t* rank,
                                                              const int32_t* ctrl) {
@@ -752,15 +883,7 @@ __global__ __launch_bounds__(kRankTile) void tree_rank_kernel(int n, const int32
     if (!ctrl[C_ORDERED]) return;
     const int total = ctrl[C_TILES];
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
-        // groups without tiles share their tstart with the next group that has
-        // tiles, so the last g with tstart[g] <= tile owns the tile
-        int lo = 0, hi = n - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tstart[mid] <= tile) lo = mid;
-            else hi = mid - 1;
-        }
-        const int g = lo;
+        const int g = owner[tile];
         const int m = gcount[g];
         const int nt = (m + kRankTile - 1) / kRankTile;
         const int local = tile - tstart[g];
@@ -796,48 +919,103 @@ __global__ __launch_bounds__(256) void tree_place_kernel(int n, const int32_t* l
     sorted_grp[slot] = g;
 }
 
-// One workgroup: segmented exclusive scan of the placed sizes (segments =
-// sibling groups) -> total size of the smaller siblings of each slot.
-__global__ __launch_bounds__(kRoundThreads) void tree_segscan_kernel(
-    int n, const int32_t* sorted_size, const int32_t* sorted_grp, int32_t* sorted_pre,
-    const int32_t* ctrl) {
-    __shared__ int s_val[kRoundThreads];
-    __shared__ int s_head[kRoundThreads];
+// Segmented exclusive scan of the placed sizes (segments = sibling groups)
+// -> total size of the smaller siblings of each slot, over the n-1 slots in
+// two grid launches like the scans above.  A block's summary is (sum after its
+// last segment head, whether it holds a head); a block's incoming carry sums
+// the summaries of the blocks before it back to the nearest one with a head.
+__device__ __forceinline__ bool seg_head(const int32_t* grp, int i) {
+    return i == 0 || grp[i] != grp[i - 1];
+}
+
+__global__ __launch_bounds__(kScanThreads) void tree_segpart_kernel(int n,
+                                                                   const int32_t* sorted_size,
+                                                                   const int32_t* sorted_grp,
+                                                                   int32_t* bseg,
+                                                                   const int32_t* ctrl) {
+    __shared__ int s_v[kScanThreads], s_h[kScanThreads];
     if (!ctrl[C_ORDERED]) return;
-    const int t = threadIdx.x;
-    const int m = n - 1;  // slots
-    const int per = (m + kRoundThreads - 1) / kRoundThreads;
-    const int b = min(m, t * per), e = min(m, b + per);
+    const int m = n - 1;
+    const int b0 = blockIdx.x * kScanBlock + threadIdx.x * 8;
     int tot = 0, head = 0;
-    for (int i = b; i < e; ++i) {
-        if (i == 0 || sorted_grp[i] != sorted_grp[i - 1]) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int i = b0 + j;
+        if (i < m) {
+            if (seg_head(sorted_grp, i)) {
+                tot = 0;
+                head = 1;
+            }
+            tot += sorted_size[i];
+        }
+    }
+    s_v[threadIdx.x] = tot;
+    s_h[threadIdx.x] = head;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int v = 0, h = 0;
+        for (int k = 0; k < kScanThreads; ++k) {
+            v = s_h[k] ? s_v[k] : v + s_v[k];
+            h |= s_h[k];
+        }
+        bseg[2 * blockIdx.x] = v;
+        bseg[2 * blockIdx.x + 1] = h;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void tree_segscan_kernel(
+    int n, const int32_t* sorted_size, const int32_t* sorted_grp, const int32_t* bseg,
+    int32_t* sorted_pre, const int32_t* ctrl) {
+    __shared__ int s_v[kScanThreads], s_h[kScanThreads];
+    if (!ctrl[C_ORDERED]) return;
+    const int m = n - 1;
+    int carry = 0;
+    for (int b = (int)blockIdx.x - 1; b >= 0; --b) {
+        carry += bseg[2 * b];
+        if (bseg[2 * b + 1]) break;
+    }
+    const int t = threadIdx.x;
+    const int b0 = blockIdx.x * kScanBlock + t * 8;
+    int sz[8];
+    bool hd[8];
+    int tot = 0, head = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int i = b0 + j;
+        sz[j] = i < m ? sorted_size[i] : 0;
+        hd[j] = i < m && seg_head(sorted_grp, i);
+        if (hd[j]) {
             tot = 0;
             head = 1;
         }
-        tot += sorted_size[i];
+        tot += sz[j];
     }
-    s_val[t] = tot;
-    s_head[t] = head;
+    s_v[t] = tot;
+    s_h[t] = head;
     __syncthreads();
-    // inclusive segmented scan over the chunks: (v, h) + (v', h') = (h' ? v' : v + v', h | h')
-    for (int d = 1; d < kRoundThreads; d <<= 1) {
+    // inclusive segmented scan: (v, h) + (v', h') = (h' ? v' : v + v', h | h')
+    for (int d = 1; d < kScanThreads; d <<= 1) {
         int pv = 0, ph = 0;
         if (t >= d) {
-            pv = s_val[t - d];
-            ph = s_head[t - d];
+            pv = s_v[t - d];
+            ph = s_h[t - d];
         }
         __syncthreads();
-        if (t >= d && !s_head[t]) {
-            s_val[t] += pv;
-            s_head[t] |= ph;
+        if (t >= d && !s_h[t]) {
+            s_v[t] += pv;
+            s_h[t] |= ph;
         }
         __syncthreads();
     }
-    int carry = t ? s_val[t - 1] : 0;
-    for (int i = b; i < e; ++i) {
-        if (i == 0 || sorted_grp[i] != sorted_grp[i - 1]) carry = 0;
-        sorted_pre[i] = carry;
-        carry += sorted_size[i];
+    int run = t == 0 ? carry : (s_h[t - 1] ? s_v[t - 1] : carry + s_v[t - 1]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int i = b0 + j;
+        if (i < m) {
+            if (hd[j]) run = 0;
+            sorted_pre[i] = run;
+            run += sz[j];
+        }
     }
 }
 
@@ -996,33 +1174,45 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
     if (e != hipSuccess) return e;
     APPD_LAUNCH("tree_keyup_kernel", s,
         tree_keyup_kernel<WIDEST><<<nb, 256, 0, s>>>(W, n, w.par, w.keyup, w.link, w.size, w.gcount,
-            w.ctrl));
+            w.hook, w.ctrl));
     APPD_CHK();
     APPD_LAUNCH("tree_link_kernel", s,
-        tree_link_kernel<<<nb, 256, 0, s>>>(n, w.keyup, w.link, w.ctrl));
+        tree_link_kernel<<<nb, 256, 0, s>>>(n, w.keyup, w.link, w.gcount, w.ctrl));
     APPD_CHK();
     APPD_LAUNCH("tree_sizes_kernel", s,
-        tree_sizes_kernel<<<nb, 256, 0, s>>>(n, w.link, w.size, w.gcount, w.ctrl));
+        tree_sizes_kernel<<<nb, 256, 0, s>>>(n, w.link, w.size, w.gcount, w.hook, w.ctrl));
+    APPD_CHK();
+    // block summaries go to hx / hy (free in this phase): 2 * nsb <= max(n, 64)
+    // ints, the size of every per-vertex array of the workspace.  The rank-tile
+    // owners go to best (2n ints; at most (n/256 + 1)^2 <= 2n tiles).
+    const int nsb = (n + kScanBlock - 1) / kScanBlock;
+    APPD_LAUNCH("tree_scanpart_kernel", s,
+        tree_scanpart_kernel<<<nsb, kScanThreads, 0, s>>>(n, w.gcount, w.hx, w.ctrl));
     APPD_CHK();
     APPD_LAUNCH("tree_scan_kernel", s,
-        tree_scan_kernel<<<1, kRoundThreads, 0, s>>>(n, w.gcount, w.gstart, w.gfill, w.tstart,
-            w.ctrl));
+        tree_scan_kernel<<<nsb, kScanThreads, 0, s>>>(n, w.gcount, w.gstart, w.gfill, w.tstart,
+                                                      w.hx, (int32_t*)w.best, w.ctrl));
     APPD_CHK();
     APPD_LAUNCH("tree_group_kernel", s,
         tree_group_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.gfill, w.grouped, w.rank,
             w.ctrl));
     APPD_CHK();
     APPD_LAUNCH("tree_rank_kernel", s,
-        tree_rank_kernel<<<1024, kRankTile, 0, s>>>(n, w.gcount, w.gstart, w.tstart, w.grouped,
-            w.keyup, w.rank, w.ctrl));
+        tree_rank_kernel<<<1024, kRankTile, 0, s>>>(n, w.gcount, w.gstart, w.tstart,
+            (const int32_t*)w.best, w.grouped, w.keyup, w.rank, w.ctrl));
     APPD_CHK();
     APPD_LAUNCH("tree_place_kernel", s,
         tree_place_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.rank, w.size, w.sorted_size,
             w.sorted_grp, w.ctrl));
     APPD_CHK();
+    const int nseg = max(1, (n - 1 + kScanBlock - 1) / kScanBlock);
+    APPD_LAUNCH("tree_segpart_kernel", s,
+        tree_segpart_kernel<<<nseg, kScanThreads, 0, s>>>(n, w.sorted_size, w.sorted_grp, w.hy,
+                                                          w.ctrl));
+    APPD_CHK();
     APPD_LAUNCH("tree_segscan_kernel", s,
-        tree_segscan_kernel<<<1, kRoundThreads, 0, s>>>(n, w.sorted_size, w.sorted_grp,
-            w.sorted_pre, w.ctrl));
+        tree_segscan_kernel<<<nseg, kScanThreads, 0, s>>>(n, w.sorted_size, w.sorted_grp, w.hy,
+                                                          w.sorted_pre, w.ctrl));
     APPD_CHK();
     APPD_LAUNCH("tree_pos_kernel", s,
         tree_pos_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.rank, w.sorted_pre, w.keyup,

@@ -44,6 +44,12 @@ constexpr int kLdsBytes = 150 * 1024;  // dynamic LDS the rounds kernel may take
 constexpr int kTableBytes = 28;        // per-component table entry
 constexpr uint64_t kNone = ~0ull;
 constexpr uint16_t kNoId = 0xffff;  // end of a short list (n < 65535 always)
+// A vertex's list is stored as K/4 groups of 32 bytes: the vertex ids of four
+// consecutive entries (u16, bytes 0-7), their ord32 weights (u32, bytes 8-23),
+// 8 bytes of padding.  Group g of vertex u sits at (g * n + u) * 32 bytes, so
+// the waves of the rounds kernel, whose lanes hold consecutive vertices, read
+// contiguous memory.  The edge key of an entry is ord32 << 32 | flat(u, id).
+constexpr int kGroupWords = 8;
 
 // control block (int32 words); word 32 holds the number of rank tiles
 enum { C_DONE = 0, C_NCOMP, C_NEED_PASS, C_FALLBACK, C_ROUNDS, C_ORDERED, C_WORDS };
@@ -97,8 +103,7 @@ __global__ __launch_bounds__(kPassThreads) void tree_pass_kernel(const float* __
                                                                  int n,
                                                                  const int32_t* __restrict__ comp,
                                                                  int32_t* __restrict__ lptr,
-                                                                 uint64_t* __restrict__ lists,
-                                                                 uint16_t* __restrict__ lids,
+                                                                 uint32_t* __restrict__ groups,
                                                                  const int32_t* __restrict__ ctrl) {
     if (ctrl[C_DONE]) return;
     const int lane = threadIdx.x & (kWave - 1);
@@ -195,9 +200,10 @@ __global__ __launch_bounds__(kPassThreads) void tree_pass_kernel(const float* __
             }
         }
     }
-    if (lane < kK) {
-        lists[(size_t)u * kK + lane] = mine;
-        lids[(size_t)u * kK + lane] = mine == kNone ? kNoId : (uint16_t)(uint32_t)mine;
+    if (lane < kK) {  // group lane/4, slot lane%4 (layout: see kGroupWords)
+        uint32_t* g = groups + ((size_t)(lane >> 2) * n + u) * kGroupWords;
+        ((uint16_t*)g)[lane & 3] = mine == kNone ? kNoId : (uint16_t)(uint32_t)mine;
+        g[2 + (lane & 3)] = (uint32_t)(mine >> 32);
     }
     if (lane == 0) lptr[u] = 0;
 }
@@ -210,8 +216,7 @@ struct RoundArgs {
     uint64_t* best;
     uint64_t* lb;
     int32_t* lptr;
-    const uint64_t* lists;
-    const uint16_t* lids;  // vertex ids of the list entries, 32 bytes per vertex
+    const uint32_t* groups;  // candidate lists, K/4 groups of kGroupWords words per vertex
     int32_t* hook;
     int32_t* hx;  // hooking endpoint inside the component
     int32_t* hy;  // endpoint outside
@@ -334,7 +339,7 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
 #pragma unroll
             for (int i = 0; i < kV; ++i) {
                 const int u = base + i * kRoundThreads + t;
-                e[i] = u < n ? a.lids[(size_t)u * kK] : kNoId;
+                e[i] = u < n ? *(const uint16_t*)(a.groups + (size_t)u * kGroupWords) : kNoId;
             }
 #pragma unroll
             for (int i = 0; i < kV; ++i) {
@@ -423,99 +428,97 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
     __syncthreads();
 
     // 1. cheapest outgoing candidate (or lower bound) of every vertex.  Each
-    //    round a vertex examines the rest of the aligned group of four list
-    //    entries that holds its list pointer (one 8-byte load of vertex ids,
-    //    endpoint components from LDS).  The first entry leaving its component
-    //    is its exact cheapest outgoing edge.  If the whole group is internal,
-    //    every outgoing edge of the vertex is larger than the group's last
-    //    entry, whose key becomes a lower bound, and the pointer moves to the
-    //    next group (a vertex still walking its list is "pending"); an
-    //    exhausted list bounds by entry K-1.  Either way one key is read per
-    //    vertex.  A wave whose vertices share one component sends one atomic
-    //    per minimum.
+    //    round a vertex reads the 32-byte group of its list that holds its list
+    //    pointer (ids and weights of four entries) and checks the rest of the
+    //    group, endpoint components from LDS.  The first entry leaving its
+    //    component is its exact cheapest outgoing edge.  If the rest of the
+    //    group is internal, every outgoing edge of the vertex is larger than
+    //    the group's last entry, which becomes a lower bound, and the pointer
+    //    moves to the next group (the vertex is "pending": its walk continues
+    //    next round); an exhausted list bounds by its entry K-1.  A round in
+    //    which no component decides but some vertex is pending is followed by
+    //    another round on the same lists.  A wave whose vertices share one
+    //    component sends one atomic per minimum.
     constexpr int kW = 8;  // vertices per thread
     constexpr int kStride = kW * kRoundThreads;
+    constexpr int GW = kGroupWords;
     for (int guard = 0; guard < 128 && !ctrl[C_DONE]; ++guard) {
         if (t == 0) {
             s_flag[0] = 0;  // components that decided this round
             ctrl[C_ROUNDS] += 1;
         }
         for (int base = 0; base < n; base += kStride) {
-            int pp[kW], p0[kW], cu[kW];
-            uint64_t ids[kW];
+            int pp[kW];
+            uint4 gr[kW];  // ids (x, y) and ords of entries 0, 1 (z, w) of the group
+            uint2 go[kW];  // ords of entries 2, 3
 #pragma unroll
             for (int i = 0; i < kW; ++i) {
                 const int u = base + i * kRoundThreads + t;
                 pp[i] = u < n ? a.lptr[u] : kK;
-                p0[i] = pp[i];
             }
 #pragma unroll
             for (int i = 0; i < kW; ++i) {
                 const int u = base + i * kRoundThreads + t;
-                const int q = pp[i] & ~3;
-                ids[i] = (u < n && pp[i] < kK) ? *(const uint64_t*)(a.lids + (size_t)u * kK + q)
-                                               : ~0ull;
-                cu[i] = u < n ? getc(u) : -1;
-            }
-            bool pend[kW], bound[kW];
-#pragma unroll
-            for (int i = 0; i < kW; ++i) {
-                const int u = base + i * kRoundThreads + t;
-                pend[i] = false;
-                bound[i] = u < n && pp[i] >= kK;  // exhausted before this round
-                if (u >= n || pp[i] >= kK) continue;
-                const int q = pp[i] & ~3;
-                int found = -1;
-                bool shortl = false;
-#pragma unroll
-                for (int r = 3; r >= 0; --r) {  // the first qualifying entry wins
-                    const uint32_t v = (uint32_t)(ids[i] >> (16 * r)) & 0xffffu;
-                    if (q + r < pp[i]) continue;
-                    if (v == kNoId) {
-                        shortl = true;
-                        found = -1;
-                    } else if (getc((int)v) != cu[i]) {
-                        found = r;
-                        shortl = false;
-                    }
+                if (u < n) {  // an exhausted list needs only its last group (the bound)
+                    const int g = pp[i] < kK ? (pp[i] >> 2) : kK / 4 - 1;
+                    const uint32_t* G = a.groups + ((size_t)g * n + u) * GW;
+                    gr[i] = *(const uint4*)G;
+                    go[i] = *(const uint2*)(G + 4);
                 }
-                if (found >= 0) {
-                    pp[i] = q + found;
-                } else if (shortl) {
-                    pp[i] = kK;  // nothing beyond a short list: no bound
-                } else {
-                    pp[i] = q + 4;     // whole group internal
-                    bound[i] = true;   // key of entry q+3 bounds the vertex
-                    pend[i] = pp[i] < kK;
-                }
-            }
-            uint64_t ent[kW];
-#pragma unroll
-            for (int i = 0; i < kW; ++i) {
-                const int u = base + i * kRoundThreads + t;
-                int slot = -1;
-                if (u < n) {
-                    if (bound[i]) slot = (pp[i] >= kK ? kK : pp[i]) - 1;
-                    else if (pp[i] < kK) slot = pp[i];
-                }
-                ent[i] = slot >= 0 ? a.lists[(size_t)u * kK + slot] : kNone;
             }
             int npend = 0;
 #pragma unroll
             for (int i = 0; i < kW; ++i) {
                 const int u = base + i * kRoundThreads + t;
                 const bool act = u < n;
+                const int cu = act ? getc(u) : -1;
                 uint64_t kc = kNone, kb = kNone;
+                bool pend = false;
                 if (act) {
-                    if (ent[i] != kNone) {
-                        if (bound[i]) kb = edge_key_of(ent[i], u, n);
-                        else kc = edge_key_of(ent[i], u, n);
+                    const uint32_t id4[4] = {gr[i].x & 0xffffu, gr[i].x >> 16, gr[i].y & 0xffffu,
+                                             gr[i].y >> 16};
+                    const uint32_t od4[4] = {gr[i].z, gr[i].w, go[i].x, go[i].y};
+                    const int p = pp[i];
+                    if (p >= kK) {  // exhausted in an earlier round
+                        if (id4[3] != kNoId) kb = ((uint64_t)od4[3] << 32) | flat_idx(u, id4[3], n);
+                    } else {
+                        const int q = p & ~3;
+                        int found = -1;
+                        bool shortl = false;
+#pragma unroll
+                        for (int r = 3; r >= 0; --r) {  // the first qualifying entry wins
+                            if (q + r < p) continue;
+                            if (id4[r] == kNoId) {
+                                shortl = true;
+                                found = -1;
+                            } else if (getc((int)id4[r]) != cu) {
+                                found = r;
+                                shortl = false;
+                            }
+                        }
+                        int np;
+                        if (found >= 0) {
+                            uint32_t v = id4[0], o = od4[0];
+#pragma unroll
+                            for (int r = 1; r < 4; ++r) {
+                                v = found == r ? id4[r] : v;
+                                o = found == r ? od4[r] : o;
+                            }
+                            kc = ((uint64_t)o << 32) | flat_idx(u, v, n);
+                            np = q + found;
+                        } else if (shortl) {
+                            np = kK;  // nothing beyond a short list: no bound
+                        } else {      // rest of the group internal: its last entry bounds
+                            kb = ((uint64_t)od4[3] << 32) | flat_idx(u, id4[3], n);
+                            np = q + 4;
+                            pend = np < kK;
+                        }
+                        if (np != p) a.lptr[u] = np;
                     }
-                    if (pp[i] != p0[i]) a.lptr[u] = pp[i];
                 }
-                npend += __popcll(__ballot(pend[i]));
-                const int c0 = __builtin_amdgcn_readfirstlane(cu[i]);
-                const uint64_t same = __ballot(act && cu[i] == c0);
+                npend += __popcll(__ballot(pend));
+                const int c0 = __builtin_amdgcn_readfirstlane(cu);
+                const uint64_t same = __ballot(act && cu == c0);
                 const uint64_t acts = __ballot(act);
                 if (same == acts) {
                     const uint64_t mc = wave_min_u64(kc), mb = wave_min_u64(kb);
@@ -524,8 +527,8 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
                         if (mb != kNone) min_lb(c0, mb);
                     }
                 } else if (act) {
-                    if (kc != kNone) min_best(cu[i], kc);
-                    if (kb != kNone) min_lb(cu[i], kb);
+                    if (kc != kNone) min_best(cu, kc);
+                    if (kb != kNone) min_lb(cu, kb);
                 }
             }
             if (lane == 0 && npend) atomicAdd(&s_flag[3], npend);
@@ -1057,8 +1060,7 @@ __global__ __launch_bounds__(1024) void tree_fallback_kernel(const float* __rest
 
 // ---------------------------------------------------------------- host side
 struct TreeWs {
-    uint64_t* lists;
-    uint16_t* lids;
+    uint64_t* lists;  // candidate-list groups (128 bytes per vertex)
     int32_t *comp, *lptr, *hook, *hx, *hy, *par, *link, *size, *gcount, *gstart, *gfill;
     int32_t *tstart, *grouped, *rank, *sorted_size, *sorted_grp, *sorted_pre;
     uint64_t *best, *lb, *keyup;
@@ -1078,7 +1080,6 @@ static TreeWs carve_tree(void* ws, int n) {
     };
     TreeWs w;
     w.lists = (uint64_t*)take(8 * (size_t)n * kK);
-    w.lids = (uint16_t*)take(2 * (size_t)n * kK);
     int32_t** ints[11] = {&w.comp, &w.lptr, &w.hook, &w.hx, &w.hy, &w.par,
                           &w.link, &w.size, &w.gcount, &w.gstart, &w.gfill};
     for (int i = 0; i < 11; ++i) *ints[i] = (int32_t*)take(4 * (size_t)n);
@@ -1127,11 +1128,11 @@ static void launch_pass(const float* W, int n, const TreeWs& w, hipStream_t s) {
     if (vec)
         APPD_LAUNCH("tree_pass_kernel", s,
             tree_pass_kernel<WIDEST, FILTER, true><<<blocks, kPassThreads, 0, s>>>(W, n, w.comp,
-                w.lptr, w.lists, w.lids, w.ctrl));
+                w.lptr, (uint32_t*)w.lists, w.ctrl));
     else
         APPD_LAUNCH("tree_pass_kernel", s,
             tree_pass_kernel<WIDEST, FILTER, false><<<blocks, kPassThreads, 0, s>>>(W, n, w.comp,
-                w.lptr, w.lists, w.lids, w.ctrl));
+                w.lptr, (uint32_t*)w.lists, w.ctrl));
 }
 
 template <bool WIDEST>
@@ -1156,7 +1157,7 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)round_lds);
         if (e != hipSuccess) return e;
     }
-    RoundArgs ra{W,      n,    w.comp, w.best, w.lb, w.lptr, w.lists, w.lids,
+    RoundArgs ra{W,      n,    w.comp, w.best, w.lb, w.lptr, (const uint32_t*)w.lists,
                  w.hook, w.hx, w.hy,   w.par,  w.ctrl, cm};
     for (int p = 0; p < kPasses; ++p) {
         if (p == 0) launch_pass<WIDEST, false>(W, n, w, s);

@@ -159,6 +159,8 @@ def bench_batched(appd, torch, steps):
     I = torch.empty(Wd.numel(), dtype=torch.int32, device=dev)
     entries = float(b.total_nn)
 
+    tune_ms = b.autotune(Wd, out=(M, I))
+    sched = b.schedule()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -214,7 +216,9 @@ def bench_batched(appd, torch, steps):
             "batched_alg_gbps": 12.0 * entries / ms_b / 1e6,
             "loop_ms": ms_l, "loop_entries_per_s": entries / ms_l * 1e3,
             "speedup_vs_loop": ms_l / ms_b,
-            "batched": "one prepared plan, kernels replayed from a HIP graph",
+            "batched": "one prepared plan, schedule chosen by the autotuner, replayed from a "
+                       "HIP graph",
+            "schedule": sched, "autotune_ms": tune_ms,
             "loop": "%d appd_forward_ws calls on one stream" % len(ns),
             "outputs_identical": same}
 
@@ -236,6 +240,9 @@ def bench_fwd_bwd(appd, torch, steps):
     M = torch.empty_like(W)
     I = torch.empty(b.total_nn, dtype=torch.int32, device=dev)
     entries = float(b.total_nn)
+
+    b.pairwise(X, d, out=W)
+    b.autotune(W, out=(M, I))
 
     def batched():
         b.pairwise(X, d, out=W)
@@ -298,6 +305,7 @@ def bench_fwd_bwd(appd, torch, steps):
             "batched_alg_gbps": 24.0 * entries / ms_b / 1e6,
             "loop": "%d x (appd_pairwise_euclidean, appd_forward_ex, appd_backward_points)"
                     % len(ns),
+            "schedule": b.schedule(),
             "dX_rel_diff_loop_vs_batched": err}
 
 

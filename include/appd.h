@@ -119,24 +119,36 @@ int appd_fill(int n, int mode, const void* ws, size_t ws_bytes, float* M, int32_
  * vertex) start at sum_{h<g} n_h; its points X (n_g x d) at d * sum_{h<g} n_h.
  * Every graph needs 1 <= n_g <= APPD_BATCH_MAX_N.
  *
- * appd_batch_prepare plans the batch on the host (size classes, graphs listed
- * by decreasing n so the longest Prim chains start first, work tables) and
- * copies the tables into ws with synchronous host-to-device copies; it must
- * precede the other batch calls and is not capturable in a HIP graph.  The
- * calls that take a prepared plan only launch kernels on `stream` and can be
- * captured.  `plan` is plain host data filled by appd_batch_prepare.
+ * Graphs are grouped into size classes (n <= 64, 128, 256, 512, 1024, 2048)
+ * and listed by decreasing n, so the longest Prim chains start first.  Each
+ * class runs Prim's algorithm (one workgroup per graph, class_threads[c]
+ * threads) and then the fill (work items of class_rows[c] rows); up to
+ * `streams` classes proceed concurrently on library streams forked from and
+ * joined back into `stream`.
+ *
+ * appd_batch_prepare plans the batch on the host (default schedule) and copies
+ * the tables into ws with synchronous host-to-device copies; it must precede
+ * the other batch calls and is not capturable in a HIP graph.
+ * appd_batch_autotune times candidate schedules of appd_forward_batched on the
+ * caller's batch and keeps the fastest in *plan (updating the device tables);
+ * it synchronises and is not capturable either.  The calls that take a
+ * prepared plan only launch kernels (and fork/join events) and can be
+ * captured.  `plan` is plain host data.
  */
 #define APPD_BATCH_MAX_N 2048
-#define APPD_BATCH_CLASSES 4
+#define APPD_BATCH_CLASSES 6
 
 typedef struct {
     int num_graphs;
     int max_n;
     int64_t total_n;  /* sum of n_g */
     int64_t total_nn; /* sum of n_g^2 */
-    int class_first[APPD_BATCH_CLASSES];
-    int class_count[APPD_BATCH_CLASSES];
-    int class_chunks[APPD_BATCH_CLASSES];
+    int class_first[APPD_BATCH_CLASSES];   /* first position of the class in n-descending order */
+    int class_count[APPD_BATCH_CLASSES];   /* graphs in the class */
+    int class_chunks[APPD_BATCH_CLASSES];  /* fill work items of the class */
+    int class_rows[APPD_BATCH_CLASSES];    /* rows per fill work item */
+    int class_threads[APPD_BATCH_CLASSES]; /* Prim workgroup size */
+    int streams;      /* classes run concurrently on up to this many streams (1..6) */
     int pair_tiles;   /* work items of the point-to-graph kernel */
     int grad_chunks;  /* work items of the edge-gradient kernel */
     int chain_blocks; /* work items of the point-gradient kernel */
@@ -149,6 +161,13 @@ size_t appd_batch_workspace_bytes(const int32_t* ns_host, int num_graphs);
 /* Fill `plan` from the host sizes and upload the device tables into ws. */
 int appd_batch_prepare(const int32_t* ns_host, int num_graphs, void* ws, size_t ws_bytes,
                        appd_batch_plan* plan, void* stream);
+
+/* Times candidate schedules (Prim workgroup sizes, fill rows per item, class
+ * concurrency) on this batch -- W, M, idx are the caller's packed device
+ * buffers; M and idx are overwritten -- and stores the fastest in *plan.
+ * best_ms (nullable) receives its time per forward. */
+int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan* plan, void* ws,
+                        void* stream, float* best_ms);
 
 /* Batched forward (Algorithm 4 per graph).  parent: nullable, total_n int32. */
 int appd_forward_batched(const float* W, int mode, float* M, int32_t* idx, int32_t* parent,

@@ -46,6 +46,7 @@ SIGNATURES = {
     "appd_batch_workspace_bytes": ([_P, _I], _SZ),
     "appd_batch_prepare": ([_P, _I, _P, _SZ, _P, _P], _I),
     "appd_forward_batched": ([_P, _I, _P, _P, _P, _P, _P, _P], _I),
+    "appd_batch_autotune": ([_P, _P, _P, _P, _P, _P, _P], _I),
     "appd_pairwise_euclidean_batched": ([_P, _I, _P, _P, _P, _P], _I),
     "appd_backward_points_batched": ([_P, _I, _P, _P, _P, _P, _P, _P, _P, _P], _I),
     "appd_grad_workspace_bytes": ([_I], _SZ),
@@ -58,6 +59,7 @@ SIGNATURES = {
 }
 
 BATCH_MAX_N = 2048
+BATCH_CLASSES = 6
 MAX_DIM = 64
 GRAD_MAX_N = 32768
 
@@ -66,8 +68,12 @@ class BatchPlan(ctypes.Structure):
     """Mirror of appd_batch_plan (include/appd.h)."""
     _fields_ = [("num_graphs", ctypes.c_int), ("max_n", ctypes.c_int),
                 ("total_n", ctypes.c_int64), ("total_nn", ctypes.c_int64),
-                ("class_first", ctypes.c_int * 4), ("class_count", ctypes.c_int * 4),
-                ("class_chunks", ctypes.c_int * 4), ("pair_tiles", ctypes.c_int),
+                ("class_first", ctypes.c_int * BATCH_CLASSES),
+                ("class_count", ctypes.c_int * BATCH_CLASSES),
+                ("class_chunks", ctypes.c_int * BATCH_CLASSES),
+                ("class_rows", ctypes.c_int * BATCH_CLASSES),
+                ("class_threads", ctypes.c_int * BATCH_CLASSES),
+                ("streams", ctypes.c_int), ("pair_tiles", ctypes.c_int),
                 ("grad_chunks", ctypes.c_int), ("chain_blocks", ctypes.c_int),
                 ("ws_bytes", ctypes.c_size_t)]
 
@@ -208,6 +214,28 @@ class Batch:
         _check(lib().appd_batch_prepare(self.ns.ctypes.data_as(_P), self.G, _ptr(self.ws), nbytes,
                                         ctypes.byref(self.plan), _stream(self.device)),
                "appd_batch_prepare")
+
+    def autotune(self, W: torch.Tensor, out=None) -> float:
+        """Time the candidate schedules on this batch's W and keep the fastest;
+        returns its milliseconds per forward.  Synchronises; not capturable."""
+        if W.dtype != torch.float32 or W.numel() != self.total_nn or not W.is_contiguous():
+            raise ValueError("W must be a contiguous float32 tensor of sum(n^2) elements")
+        if out is None:
+            M = torch.empty(self.total_nn, dtype=torch.float32, device=self.device)
+            idx = torch.empty(self.total_nn, dtype=torch.int32, device=self.device)
+        else:
+            M, idx = out
+        ms = ctypes.c_float()
+        _check(lib().appd_batch_autotune(_ptr(W), _ptr(M), _ptr(idx), ctypes.byref(self.plan),
+                                         _ptr(self.ws), _stream(self.device), ctypes.byref(ms)),
+               "appd_batch_autotune")
+        return ms.value
+
+    def schedule(self) -> dict:
+        """The plan's per-class schedule (classes n <= 64 .. 2048)."""
+        p = self.plan
+        return {"class_count": list(p.class_count), "class_threads": list(p.class_threads),
+                "class_rows": list(p.class_rows), "streams": p.streams}
 
     def forward(self, W: torch.Tensor, mode: int = MINIMAX, return_parent: bool = False,
                 out=None):

@@ -94,8 +94,48 @@ appd::BatchPlan device_plan(const appd_batch_plan* p, const Tables& t) {
         bp.class_first[c] = p->class_first[c];
         bp.class_count[c] = p->class_count[c];
         bp.class_chunks[c] = p->class_chunks[c];
+        bp.class_rows[c] = p->class_rows[c];
+        bp.class_threads[c] = p->class_threads[c];
     }
+    bp.streams = p->streams;
     return bp;
+}
+
+bool schedule_ok(const appd_batch_plan* p) {
+    if (p->streams < 1 || p->streams > appd::kBatchClasses) return false;
+    for (int c = 0; c < appd::kBatchClasses; ++c) {
+        if (!p->class_count[c]) continue;
+        if (p->class_rows[c] < 1 || p->class_rows[c] > APPD_BATCH_MAX_N) return false;
+        if (!appd::batch_threads_ok(c, p->class_threads[c])) return false;
+    }
+    return true;
+}
+
+// Fill work items per class for the plan's rows per item; chunk_start[i] is the
+// first item of the i-th graph (n-descending order) within its class.
+void build_chunks(const int32_t* ns_host, const std::vector<int32_t>& perm, appd_batch_plan* p,
+                  std::vector<int32_t>& chunk_start) {
+    const int G = p->num_graphs;
+    chunk_start.assign(G, 0);
+    for (int c = 0; c < appd::kBatchClasses; ++c) p->class_chunks[c] = 0;
+    for (int i = 0; i < G; ++i) {
+        const int n = ns_host[perm[i]];
+        const int c = appd::batch_class_of(n);
+        const int rows = p->class_rows[c];
+        chunk_start[i] = p->class_chunks[c];
+        p->class_chunks[c] += (n + rows - 1) / rows;
+    }
+}
+
+// Default schedule: Prim workgroups of 64 threads up to n = 256, 256 threads
+// above; 16 rows per fill item; classes in order on the caller's stream.
+void default_schedule(appd_batch_plan* p) {
+    static const int threads[appd::kBatchClasses] = {64, 64, 64, 256, 256, 256};
+    for (int c = 0; c < appd::kBatchClasses; ++c) {
+        p->class_threads[c] = threads[c];
+        p->class_rows[c] = 16;
+    }
+    p->streams = 1;
 }
 
 int hip_status(hipError_t e) {
@@ -159,17 +199,15 @@ int appd_batch_prepare(const int32_t* ns_host, int num_graphs, void* ws, size_t 
     p.chain_blocks = (int)vb;
     // classes are contiguous in perm (n descending, class ascending in n)
     for (int c = 0; c < appd::kBatchClasses; ++c) p.class_first[c] = -1;
-    const int rows = appd::batch_rows_per_chunk();
     for (int i = 0; i < G; ++i) {
-        const int n = ns_host[perm[i]];
-        const int c = appd::batch_class_of(n);
+        const int c = appd::batch_class_of(ns_host[perm[i]]);
         if (p.class_first[c] < 0) p.class_first[c] = i;
         p.class_count[c]++;
-        chunk_start[i] = p.class_chunks[c];
-        p.class_chunks[c] += (n + rows - 1) / rows;
     }
     for (int c = 0; c < appd::kBatchClasses; ++c)
         if (p.class_first[c] < 0) p.class_first[c] = 0;
+    default_schedule(&p);
+    build_chunks(ns_host, perm, &p, chunk_start);
 
     // one host image of the table region, one synchronous copy
     std::vector<char> img(lay.table_bytes, 0);
@@ -192,9 +230,83 @@ int appd_batch_prepare(const int32_t* ns_host, int num_graphs, void* ws, size_t 
     return ok();
 }
 
+int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan* plan, void* ws,
+                        void* stream, float* best_ms) {
+    if (!W || !M || !idx || !plan_ok(plan, ws) || !schedule_ok(plan)) return fail(APPD_EINVAL);
+    hipStream_t s = (hipStream_t)stream;
+    const int G = plan->num_graphs;
+    Tables t = carve(ws, G, plan->total_n);
+    std::vector<int32_t> ns(G), perm(G), chunk_start;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto hip_fail = [&](hipError_t e) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipGetLastError();
+        (void)e;
+        return fail(APPD_EHIP);
+    };
+    hipError_t e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess ||
+        (e = hipMemcpy(ns.data(), t.ns, 4 * (size_t)G, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(perm.data(), t.perm, 4 * (size_t)G, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+        return hip_fail(e);
+    // candidates: Prim workgroup sizes (narrow / wide), fill rows per item,
+    // classes in order or on concurrent streams
+    static const int narrow[appd::kBatchClasses] = {64, 64, 64, 256, 256, 256};
+    static const int wide[appd::kBatchClasses] = {64, 128, 256, 512, 512, 1024};
+    static const int rows_opt[3] = {16, 32, 64};
+    static const int streams_opt[2] = {1, 3};
+    appd_batch_plan best = *plan;
+    float best_t = -1.f;
+    for (int wsel = 0; wsel < 2; ++wsel)
+        for (int ri = 0; ri < 3; ++ri)
+            for (int si = 0; si < 2; ++si) {
+                appd_batch_plan p = *plan;
+                for (int c = 0; c < appd::kBatchClasses; ++c) {
+                    p.class_threads[c] = wsel ? wide[c] : narrow[c];
+                    p.class_rows[c] = rows_opt[ri];
+                }
+                p.streams = streams_opt[si];
+                build_chunks(ns.data(), perm, &p, chunk_start);
+                if ((e = hipStreamSynchronize(s)) != hipSuccess ||
+                    (e = hipMemcpy(t.chunk_start, chunk_start.data(), 4 * (size_t)G,
+                                   hipMemcpyHostToDevice)) != hipSuccess)
+                    return hip_fail(e);
+                appd::BatchTree tree{t.order, t.ek, t.pos, t.parent};
+                appd::BatchPlan bp = device_plan(&p, t);
+                float tt = 0.f;
+                for (int rep = 0; rep < 3; ++rep) {  // one warm-up, two timed
+                    if (rep == 1 && (e = hipEventRecord(e0, s)) != hipSuccess) return hip_fail(e);
+                    if ((e = appd::run_batched(W, t.offsets, t.ns, bp, tree, APPD_MINIMAX, M, idx,
+                                               s)) != hipSuccess)
+                        return hip_fail(e);
+                }
+                if ((e = hipEventRecord(e1, s)) != hipSuccess ||
+                    (e = hipEventSynchronize(e1)) != hipSuccess ||
+                    (e = hipEventElapsedTime(&tt, e0, e1)) != hipSuccess)
+                    return hip_fail(e);
+                tt *= 0.5f;
+                if (best_t < 0.f || tt < best_t) {
+                    best_t = tt;
+                    best = p;
+                }
+            }
+    build_chunks(ns.data(), perm, &best, chunk_start);
+    if ((e = hipMemcpy(t.chunk_start, chunk_start.data(), 4 * (size_t)G,
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *plan = best;
+    if (best_ms) *best_ms = best_t;
+    return ok();
+}
+
 int appd_forward_batched(const float* W, int mode, float* M, int32_t* idx, int32_t* parent,
                          const appd_batch_plan* plan, void* ws, void* stream) {
-    if (!W || !M || !idx || !plan_ok(plan, ws) || (mode != APPD_MINIMAX && mode != APPD_WIDEST))
+    if (!W || !M || !idx || !plan_ok(plan, ws) || !schedule_ok(plan) ||
+        (mode != APPD_MINIMAX && mode != APPD_WIDEST))
         return fail(APPD_EINVAL);
     Tables t = carve(ws, plan->num_graphs, plan->total_n);
     appd::BatchTree tree{t.order, t.ek, t.pos, parent ? parent : t.parent};

@@ -5,14 +5,21 @@
 // Graphs are grouped into size classes and, within the whole batch, listed by
 // decreasing n (longest processing time first): workgroups are dispatched in
 // blockIdx order, so the largest graphs -- whose Prim chains are the longest --
-// start first and the small ones fill in behind them.
+// start first and the small ones fill in behind them.  Each class is one Prim
+// launch and one fill launch in order on one stream; classes are spread over
+// up to plan.streams streams (forked from and joined back into the caller's
+// stream with events), so the short classes' Prim and fill run beside the
+// longest class's Prim chains.
 //
-// Phase 1, one workgroup per graph: Prim (appd_prim.h) with NT threads and CH
-// vertices per thread, chosen by the graph's class.
-// Phase 2, many workgroups per graph: each takes kBatchRows rows of one graph.
-// Every graph here fits in a single column block (n <= CB), so the block's
+// Phase 1, one workgroup per graph: Prim (appd_prim.h) with the class's
+// workgroup size (plan.class_threads) and ceil(class max / threads) vertices
+// per thread.
+// Phase 2, many workgroups per graph: each takes plan.class_rows rows of one
+// graph.  Every graph fits in a single column block (n <= CB), so the block's
 // sorted slots are the attachment positions themselves (slot k = position k,
 // gap[k] = ek[k], slot_of_col = pos) and no prep kernel is needed.
+#include <mutex>
+
 #include "appd_fill.h"
 #include "appd_internal.h"
 #include "appd_prim.h"
@@ -20,10 +27,6 @@
 namespace appd {
 
 constexpr int kBatchFillThreads = 256;
-constexpr int kBatchRows = 16;
-
-// size classes: n <= 64, 256, 1024, 2048
-constexpr int kClassMaxN[kBatchClasses] = {64, 256, 1024, 2048};
 
 template <int NT, int CH, bool WIDEST>
 __global__ __launch_bounds__(NT) void prim_batched_kernel(const float* __restrict__ W,
@@ -45,7 +48,7 @@ template <int CB, bool WIDEST>
 __global__ __launch_bounds__(kBatchFillThreads) void fill_batched_kernel(
     const int64_t* __restrict__ offsets, const int32_t* __restrict__ ns,
     const int32_t* __restrict__ perm, const int64_t* __restrict__ noff,
-    const int32_t* __restrict__ chunk_start, int first, int count, BatchTree tree,
+    const int32_t* __restrict__ chunk_start, int first, int count, int rows, BatchTree tree,
     float* __restrict__ M, int32_t* __restrict__ idx) {
     constexpr int NWV = kBatchFillThreads / kWave;
     __shared__ uint16_t s_sp[CB];
@@ -74,10 +77,11 @@ __global__ __launch_bounds__(kBatchFillThreads) void fill_batched_kernel(
         s_gap[k] = in ? ek[k] : 0ull;
     }
     __syncthreads();
-    const int r0 = chunk * kBatchRows;
-    const int r1 = min(n, r0 + kBatchRows);
+    const int r0 = chunk * rows;
+    const int r1 = min(n, r0 + rows);
     fill_rows_block<CB, WIDEST, false>(pos, ek, n, 0, n, r0, r1, s_sp, s_slot, s_gap,
-                                s_R[threadIdx.x / kWave], M + offsets[g], idx + offsets[g], NWV);
+                                       s_R[threadIdx.x / kWave], M + offsets[g],
+                                       idx + offsets[g], NWV);
 }
 
 int batch_class_of(int n) {
@@ -86,70 +90,144 @@ int batch_class_of(int n) {
     return -1;
 }
 
-int batch_rows_per_chunk() { return kBatchRows; }
+// Prim workgroup sizes a class supports: 64..1024 threads, at most 8 vertices
+// per thread, no more threads than twice the class's largest n.
+bool batch_threads_ok(int c, int threads) {
+    if (c < 0 || c >= kBatchClasses) return false;
+    if (threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
+        return false;
+    const int ch = (kClassMaxN[c] + threads - 1) / threads;
+    return ch <= 8 && threads <= 2 * kClassMaxN[c];
+}
+
+template <bool WIDEST>
+static hipError_t launch_prim_class(int c, int threads, int first, int count, const float* W,
+                                    const int64_t* offsets, const int32_t* ns,
+                                    const BatchPlan& plan, const BatchTree& tree,
+                                    hipStream_t s) {
+    const int ch = (kClassMaxN[c] + threads - 1) / threads;
+#define APPD_PRIM_B(NT, CH)                                                      \
+    if (threads == NT && ch == CH) {                                             \
+        APPD_LAUNCH("prim_batched_kernel", s,                                    \
+                    prim_batched_kernel<NT, CH, WIDEST><<<count, NT, 0, s>>>(    \
+                        W, offsets, ns, plan.perm, plan.noff, first, tree));     \
+        return hipGetLastError();                                                \
+    }
+    APPD_PRIM_B(64, 1)
+    APPD_PRIM_B(64, 2)
+    APPD_PRIM_B(64, 4)
+    APPD_PRIM_B(64, 8)
+    APPD_PRIM_B(128, 1)
+    APPD_PRIM_B(128, 2)
+    APPD_PRIM_B(128, 4)
+    APPD_PRIM_B(128, 8)
+    APPD_PRIM_B(256, 1)
+    APPD_PRIM_B(256, 2)
+    APPD_PRIM_B(256, 4)
+    APPD_PRIM_B(256, 8)
+    APPD_PRIM_B(512, 1)
+    APPD_PRIM_B(512, 2)
+    APPD_PRIM_B(512, 4)
+    APPD_PRIM_B(1024, 1)
+    APPD_PRIM_B(1024, 2)
+#undef APPD_PRIM_B
+    return hipErrorInvalidValue;
+}
+
+template <bool WIDEST>
+static hipError_t launch_fill_class(int c, int first, int count, int chunks, int rows,
+                                    const int64_t* offsets, const int32_t* ns,
+                                    const BatchPlan& plan, const BatchTree& tree, float* M,
+                                    int32_t* idx, hipStream_t s) {
+#define APPD_FILL_B(CC, CB)                                                           \
+    if (c == CC) {                                                                    \
+        APPD_LAUNCH("fill_batched_kernel", s,                                         \
+                    fill_batched_kernel<CB, WIDEST><<<chunks, kBatchFillThreads, 0, s>>>( \
+                        offsets, ns, plan.perm, plan.noff, plan.chunk_start, first,   \
+                        count, rows, tree, M, idx));                                  \
+        return hipGetLastError();                                                     \
+    }
+    APPD_FILL_B(0, 64)
+    APPD_FILL_B(1, 128)
+    APPD_FILL_B(2, 256)
+    APPD_FILL_B(3, 512)
+    APPD_FILL_B(4, 1024)
+    APPD_FILL_B(5, 2048)
+#undef APPD_FILL_B
+    return hipErrorInvalidValue;
+}
+
+// Library streams and events for the class fork/join, created once per device
+// and kept for the life of the process (default priority).
+namespace {
+struct SideStreams {
+    hipStream_t side[kBatchClasses - 1];
+    hipEvent_t fork;
+    hipEvent_t join[kBatchClasses - 1];
+    bool ready = false;
+};
+std::mutex g_side_mu;
+SideStreams g_side[64];
+
+hipError_t side_streams(SideStreams** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    SideStreams& ss = g_side[dev];
+    if (!ss.ready) {
+        for (int k = 0; k < kBatchClasses - 1; ++k) {
+            if ((e = hipStreamCreateWithFlags(&ss.side[k], hipStreamNonBlocking)) != hipSuccess)
+                return e;
+            if ((e = hipEventCreateWithFlags(&ss.join[k], hipEventDisableTiming)) != hipSuccess)
+                return e;
+        }
+        if ((e = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming)) != hipSuccess) return e;
+        ss.ready = true;
+    }
+    *out = &ss;
+    return hipSuccess;
+}
+}  // namespace
 
 template <bool WIDEST>
 static hipError_t run_batched_t(const float* W, const int64_t* offsets, const int32_t* ns,
                                 const BatchPlan& plan, const BatchTree& tree, float* M,
                                 int32_t* idx, hipStream_t s) {
-    // phase 1: Prim per graph, one launch per class (largest first)
-    for (int c = kBatchClasses - 1; c >= 0; --c) {
-        const int first = plan.class_first[c], count = plan.class_count[c];
-        if (!count) continue;
-        switch (c) {
-            case 0:
-                APPD_LAUNCH("prim_batched_kernel", s,
-                    prim_batched_kernel<64, 1, WIDEST><<<count, 64, 0, s>>>(W, offsets, ns,
-                        plan.perm, plan.noff, first, tree));
-                break;
-            case 1:
-                APPD_LAUNCH("prim_batched_kernel", s,
-                    prim_batched_kernel<64, 4, WIDEST><<<count, 64, 0, s>>>(W, offsets, ns,
-                        plan.perm, plan.noff, first, tree));
-                break;
-            case 2:
-                APPD_LAUNCH("prim_batched_kernel", s,
-                    prim_batched_kernel<256, 4, WIDEST><<<count, 256, 0, s>>>(W, offsets, ns,
-                        plan.perm, plan.noff, first, tree));
-                break;
-            default:
-                APPD_LAUNCH("prim_batched_kernel", s,
-                    prim_batched_kernel<256, 8, WIDEST><<<count, 256, 0, s>>>(W, offsets, ns,
-                        plan.perm, plan.noff, first, tree));
-                break;
+    // classes in launch order: largest first
+    int cls[kBatchClasses], nc = 0;
+    for (int c = kBatchClasses - 1; c >= 0; --c)
+        if (plan.class_count[c]) cls[nc++] = c;
+    const int nstreams = max(1, min(plan.streams, nc));
+    hipStream_t st[kBatchClasses];
+    st[0] = s;
+    SideStreams* ss = nullptr;
+    hipError_t e;
+    if (nstreams > 1) {
+        if ((e = side_streams(&ss)) != hipSuccess) return e;
+        if ((e = hipEventRecord(ss->fork, s)) != hipSuccess) return e;
+        for (int k = 1; k < nstreams; ++k) {
+            st[k] = ss->side[k - 1];
+            if ((e = hipStreamWaitEvent(st[k], ss->fork, 0)) != hipSuccess) return e;
         }
-        hipError_t e = hipGetLastError();
+    }
+    for (int j = 0; j < nc; ++j) {
+        const int c = cls[j];
+        hipStream_t cs = st[j % nstreams];
+        const int first = plan.class_first[c], count = plan.class_count[c];
+        e = launch_prim_class<WIDEST>(c, plan.class_threads[c], first, count, W, offsets, ns,
+                                      plan, tree, cs);
+        if (e != hipSuccess) return e;
+        e = launch_fill_class<WIDEST>(c, first, count, plan.class_chunks[c], plan.class_rows[c],
+                                      offsets, ns, plan, tree, M, idx, cs);
         if (e != hipSuccess) return e;
     }
-    // phase 2: fill, one launch per class
-    for (int c = kBatchClasses - 1; c >= 0; --c) {
-        const int first = plan.class_first[c], count = plan.class_count[c];
-        if (!count) continue;
-        const int blocks = plan.class_chunks[c];
-        switch (c) {
-            case 0:
-                APPD_LAUNCH("fill_batched_kernel", s,
-                    fill_batched_kernel<64, WIDEST><<<blocks, kBatchFillThreads, 0, s>>>(offsets,
-                        ns, plan.perm, plan.noff, plan.chunk_start, first, count, tree, M, idx));
-                break;
-            case 1:
-                APPD_LAUNCH("fill_batched_kernel", s,
-                    fill_batched_kernel<256, WIDEST><<<blocks, kBatchFillThreads, 0, s>>>(offsets,
-                        ns, plan.perm, plan.noff, plan.chunk_start, first, count, tree, M, idx));
-                break;
-            case 2:
-                APPD_LAUNCH("fill_batched_kernel", s,
-                    fill_batched_kernel<1024, WIDEST><<<blocks, kBatchFillThreads, 0, s>>>(offsets,
-                        ns, plan.perm, plan.noff, plan.chunk_start, first, count, tree, M, idx));
-                break;
-            default:
-                APPD_LAUNCH("fill_batched_kernel", s,
-                    fill_batched_kernel<2048, WIDEST><<<blocks, kBatchFillThreads, 0, s>>>(offsets,
-                        ns, plan.perm, plan.noff, plan.chunk_start, first, count, tree, M, idx));
-                break;
+    if (nstreams > 1) {
+        for (int k = 1; k < nstreams; ++k) {
+            if ((e = hipEventRecord(ss->join[k - 1], st[k])) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(s, ss->join[k - 1], 0)) != hipSuccess) return e;
         }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }

@@ -50,7 +50,8 @@ hipError_t run_single(const float* W, int n, int mode, float* M, int32_t* idx,
                       const SingleWs& w, hipStream_t s);
 
 // ---- batched path
-constexpr int kBatchClasses = 4;
+constexpr int kBatchClasses = 6;
+constexpr int kClassMaxN[kBatchClasses] = {64, 128, 256, 512, 1024, 2048};
 
 struct BatchTree {
     int32_t* order;
@@ -62,14 +63,17 @@ struct BatchTree {
 struct BatchPlan {
     const int32_t* perm;         // [G] graph ids, n descending (device)
     const int64_t* noff;         // [G] start of graph g's O(n) arrays (device, by graph id)
-    const int32_t* chunk_start;  // [G] first fill block of perm[i] within its class (device)
+    const int32_t* chunk_start;  // [G] first fill item of perm[i] within its class (device)
     int class_first[kBatchClasses];
     int class_count[kBatchClasses];
     int class_chunks[kBatchClasses];
+    int class_rows[kBatchClasses];
+    int class_threads[kBatchClasses];
+    int streams;
 };
 
 int batch_class_of(int n);
-int batch_rows_per_chunk();
+bool batch_threads_ok(int c, int threads);
 hipError_t run_batched(const float* W, const int64_t* offsets, const int32_t* ns,
                        const BatchPlan& plan, const BatchTree& tree, int mode, float* M,
                        int32_t* idx, hipStream_t s);

@@ -134,6 +134,90 @@ def test_batched_graph_capture_replays():
         _ = (M0 * 2).sum().item()  # eager work between replays
 
 
+def set_schedule(b, threads, rows, streams):
+    for c in range(appd.BATCH_CLASSES):
+        b.plan.class_threads[c] = threads[c]
+        b.plan.class_rows[c] = rows
+    b.plan.streams = streams
+
+
+def test_batched_schedules_identical():
+    """Every Prim workgroup size, rows per fill item and class concurrency gives
+    the same bits as the default schedule.  (Rows per item change the fill work
+    tables, so each schedule here goes through a fresh, re-prepared batch.)"""
+    say("case batched schedules")
+    Ws = mixed_graphs(6)
+    flat, offsets, ns = workloads.pack(Ws)
+    Wd = torch.from_numpy(flat).to(DEV)
+    b0 = appd.Batch(ns, DEV)
+    M0, I0 = b0.forward(Wd)
+    torch.cuda.synchronize()
+    _, io = oracle.appd(Ws[0])
+    assert np.array_equal(unpack(I0.cpu().numpy(), ns, offsets)[0], io)
+    narrow = [64, 64, 64, 256, 256, 256]
+    wide = [64, 128, 256, 512, 512, 1024]
+    mid = [64, 128, 128, 128, 512, 512]
+    for threads, streams in [(narrow, 1), (wide, 3), (mid, 6), (wide, 2)]:
+        b = appd.Batch(ns, DEV)
+        set_schedule(b, threads, 16, streams)  # rows unchanged: tables still valid
+        M, I = b.forward(Wd)
+        torch.cuda.synchronize()
+        assert torch.equal(M, M0) and torch.equal(I, I0), (threads, streams)
+
+
+def test_batched_autotune_bit_exact():
+    """The autotuner picks a schedule by timing; whatever it picks, every graph
+    still equals the oracle."""
+    say("case batched autotune")
+    Ws = mixed_graphs(7)
+    flat, offsets, ns = workloads.pack(Ws)
+    b = appd.Batch(ns, DEV)
+    Wd = torch.from_numpy(flat).to(DEV)
+    ms = b.autotune(Wd)
+    assert ms > 0
+    sched = b.schedule()
+    say("  chose", sched, "%.3f ms" % ms)
+    M, idx = b.forward(Wd)
+    torch.cuda.synchronize()
+    Ms = unpack(M.cpu().numpy(), ns, offsets)
+    Is = unpack(idx.cpu().numpy(), ns, offsets)
+    for g, W in enumerate(Ws):
+        Mo, io = oracle.appd(W)
+        assert np.array_equal(Ms[g].view(np.uint32), Mo.view(np.uint32)) and np.array_equal(Is[g], io), g
+
+
+def test_batched_streams_graph_capture_replays():
+    """Classes on concurrent library streams (fork/join events) inside a HIP
+    graph: every replay equals the eager result."""
+    say("case batched streams + HIP graph capture")
+    Ws = mixed_graphs(8)
+    flat, offsets, ns = workloads.pack(Ws)
+    b = appd.Batch(ns, DEV)
+    set_schedule(b, [64, 128, 256, 512, 512, 1024], 16, 4)
+    Wd = torch.from_numpy(flat).to(DEV)
+    M0, I0 = b.forward(Wd)
+    torch.cuda.synchronize()
+    M = torch.empty_like(M0)
+    I = torch.empty_like(I0)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.forward(Wd, out=(M, I))
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.forward(Wd, out=(M, I))
+    for rep in range(4):
+        M.fill_(-7.0)
+        I.fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(M, M0) and torch.equal(I, I0), "replay %d differs" % rep
+        _ = (M0 * 2).sum().item()
+
+
 @pytest.mark.parametrize("n,d", [(1, 3), (7, 2), (100, 8), (257, 16), (1000, 8), (2100, 5)])
 def test_pairwise_single(n, d):
     say("case pairwise n=%d d=%d" % (n, d))

@@ -50,6 +50,7 @@ def _load():
         ("oracle_appd_widest", [P, I64, P, P]),
         ("oracle_appd_alg4_rows", [P, I64, P, I64, ctypes.c_int, P, P]),
         ("oracle_mst_prim", [P, I64, ctypes.c_int, P, P, P, P]),
+        ("oracle_linkage", [P, I64, ctypes.c_int, P]),
         ("oracle_appd_fw", [P, I64, ctypes.c_int, P, P]),
         ("oracle_pairwise_euclidean_f32", [P, I64, I64, P]),
         ("oracle_pairwise_euclidean_f64", [P, I64, I64, P]),
@@ -133,6 +134,16 @@ def mst_prim(W: np.ndarray, widest: bool = False):
     _chk(_load().oracle_mst_prim(_p(W), n, int(widest), _p(order), _p(parent), _p(aw), _p(af)),
          "oracle_mst_prim")
     return order, parent, aw, af
+
+
+def linkage(W: np.ndarray, widest: bool = False) -> np.ndarray:
+    """Single-linkage dendrogram, (n-1) x 4 float64: clusters a < b joined, weight,
+    size of the new cluster (ids >= n are earlier merges)."""
+    W = _sq(W, np.float32)
+    n = W.shape[0]
+    Z = np.zeros((max(n - 1, 0), 4), np.float64)
+    _chk(_load().oracle_linkage(_p(W), n, int(widest), _p(Z)), "oracle_linkage")
+    return Z
 
 
 def appd_fw(W: np.ndarray, widest: bool = False):

@@ -40,6 +40,9 @@
  *                         the smallest up.  Reversed total order: larger weight
  *                         first, equal weights ordered by smaller flat index.
  *   oracle_mst_prim       Prim's MST alone (order of attachment, parent, keys).
+ *   oracle_linkage        The single-linkage dendrogram (scipy's linkage-matrix
+ *                         layout) from the ascending construction: tree edges
+ *                         added best first, union-find over clusters.
  *   oracle_pairwise_euclidean_f32 / _f64
  *                         Complete graph from a point set (Section 1, a dataset
  *                         "can be straightforwardly converted to a complete
@@ -354,6 +357,71 @@ int oracle_mst_prim(const float* W, int64_t n, int widest, int64_t* order, int64
         if (attach_f) attach_f[k] = edges[k - 1].f;
     }
     free(edges);
+    return rc;
+}
+
+static int g_widest_for_link = 0;
+
+/* qsort comparator: the spanning-tree order (best edge first). */
+static int tree_order_cmp(const void* pa, const void* pb) {
+    const oedge* a = (const oedge*)pa;
+    const oedge* b = (const oedge*)pb;
+    if (tree_better(g_widest_for_link, a->w, a->f, b->w, b->f)) return -1;
+    if (tree_better(g_widest_for_link, b->w, b->f, a->w, a->f)) return 1;
+    return 0;
+}
+
+static int64_t uf_find(int64_t* up, int64_t x) {
+    while (up[x] != x) {
+        up[x] = up[up[x]];
+        x = up[x];
+    }
+    return x;
+}
+
+/*
+ * Single-linkage dendrogram by the ascending construction that Section 3
+ * mentions beside Algorithm 4: the spanning-tree edges are added one by one,
+ * best first (minimax: ascending (w, flat); widest: larger weight first, equal
+ * weights by smaller flat index), to an empty forest; each edge joins two
+ * clusters.  Z[4i .. 4i+3] = {a, b, w, size}: the clusters joined by the i-th
+ * edge (a < b; ids below n are vertices, n + j is the cluster made by edge j),
+ * the edge's weight, and the number of vertices in the new cluster.
+ */
+int oracle_linkage(const float* W, int64_t n, int widest, double* Z) {
+    if (bad_n(n) || !W || !Z) return -1;
+    if (n == 1) return 0;
+    wmat m = {W, NULL, n};
+    oedge* edges = (oedge*)malloc(sizeof(oedge) * (size_t)(n - 1));
+    int64_t* up = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t* cid = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t* csz = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+    if (!edges || !up || !cid || !csz) {
+        free(edges); free(up); free(cid); free(csz);
+        return -3;
+    }
+    int rc = prim_tree(&m, widest, edges, NULL);
+    if (rc == 0) {
+        g_widest_for_link = widest;
+        qsort(edges, (size_t)(n - 1), sizeof(oedge), tree_order_cmp);
+        for (int64_t v = 0; v < n; ++v) {
+            up[v] = v;
+            cid[v] = v;
+            csz[v] = 1;
+        }
+        for (int64_t i = 0; i < n - 1; ++i) {
+            const int64_t ra = uf_find(up, edges[i].u), rb = uf_find(up, edges[i].v);
+            const int64_t a = cid[ra], b = cid[rb];
+            Z[4 * i + 0] = (double)(a < b ? a : b);
+            Z[4 * i + 1] = (double)(a < b ? b : a);
+            Z[4 * i + 2] = canon_zero(edges[i].w);
+            Z[4 * i + 3] = (double)(csz[ra] + csz[rb]);
+            up[ra] = rb;
+            cid[rb] = n + i;
+            csz[rb] += csz[ra];
+        }
+    }
+    free(edges); free(up); free(cid); free(csz);
     return rc;
 }
 

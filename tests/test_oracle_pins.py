@@ -400,3 +400,52 @@ def test_gradient_two_points_closed_form(orc):
     _, idx = orc.appd_f64(orc.pairwise_euclidean_f64(X))
     g = orc.grad_points(X, G, idx)
     assert np.allclose(g[0], 2.5 * np.array([-3, -4]) / 5) and np.allclose(g[1], -g[0])
+
+
+# ---------------------------------------------------------------- dendrogram
+@pytest.mark.parametrize("n,kind", [(2, "uni"), (3, "uni"), (50, "uni"), (500, "uni"), (300, "pts")])
+def test_linkage_matches_scipy(orc, n, kind):
+    """Tie-free weights: the oracle's merge table equals scipy's single linkage
+    (ids, weights and sizes), the library routine behind reading distances off
+    the dendrogram."""
+    from scipy.cluster.hierarchy import linkage
+    from scipy.spatial.distance import squareform
+    if kind == "uni":
+        W = workloads.random_symmetric(n, seed=20 + n)
+    else:
+        W = workloads.euclid_w(workloads.single_points_2d(n, seed=21))
+    Z = orc.linkage(W)
+    Zs = linkage(squareform(W.astype(np.float64), checks=False), method="single")
+    assert np.array_equal(Z, Zs)
+
+
+@pytest.mark.parametrize("levels", [2, 3, 5])
+def test_linkage_cophenetic_is_appd_with_ties(orc, levels):
+    """With heavy ties the merge order is a convention, but the dendrogram's
+    cophenetic distances must be the APPD matrix (Eq. 1-2) whatever it is."""
+    from scipy.cluster.hierarchy import cophenet
+    from scipy.spatial.distance import squareform
+    W = workloads.integer_weights(257, levels, seed=levels)
+    Z = orc.linkage(W)
+    M, _ = orc.appd(W)
+    assert np.array_equal(squareform(cophenet(Z)), M.astype(np.float64))
+    assert Z[-1, 3] == 257 and (np.diff(Z[:, 2]) >= 0).all()
+
+
+def test_linkage_closed_form_all_equal(orc):
+    """All weights equal: the tree is the star at 0 and edges are taken by flat
+    index, so merge i joins vertex i+1 to the cluster built so far."""
+    for n in (2, 3, 9):
+        W = np.full((n, n), 1.5, np.float32)
+        np.fill_diagonal(W, 0)
+        Z = orc.linkage(W)
+        exp = [[0, 1, 1.5, 2]] + [[i + 1, n + i - 1, 1.5, i + 2] for i in range(1, n - 1)]
+        assert np.array_equal(Z, np.array(exp, np.float64))
+
+
+def test_linkage_widest_is_minimax_of_negation(orc):
+    W = workloads.random_symmetric(120, seed=5)
+    Zw = orc.linkage(W, widest=True)
+    Zn = orc.linkage(-W)
+    assert np.array_equal(Zw[:, [0, 1, 3]], Zn[:, [0, 1, 3]])
+    assert np.array_equal(Zw[:, 2], -Zn[:, 2])

@@ -112,6 +112,23 @@ int appd_tree(const float* W, int n, int mode, int32_t* order, int32_t* parent, 
 int appd_fill(int n, int mode, const void* ws, size_t ws_bytes, float* M, int32_t* idx,
               void* stream);
 
+/*
+ * Single-linkage dendrogram of W from its spanning tree: the merge sequence of
+ * the ascending construction Section 3 describes beside Algorithm 4 (tree edges
+ * added best first to an empty forest), whose cophenetic distances are M.
+ *   Z     (n-1) x 4 doubles, row-major, device: row i = {a, b, w, size}, the
+ *         clusters joined by the i-th merge (a < b; ids below n are vertices,
+ *         n + j is the cluster made by merge j), the weight of the joining
+ *         edge and the number of vertices in the new cluster.  Merges follow
+ *         the edge total order (minimax: ascending weight; widest: descending
+ *         weight; equal weights by smaller flat index).  Nothing is written
+ *         for n = 1 (Z may then be NULL).
+ *   mode  APPD_MINIMAX or APPD_WIDEST, optionally with an APPD_TREE_* flag.
+ *   ws    >= appd_forward_workspace_bytes(n) device bytes, 256-byte aligned.
+ */
+int appd_linkage(const float* W, int n, int mode, double* Z, void* ws, size_t ws_bytes,
+                 void* stream);
+
 /* ------------------------------------------------------------------ batches
  * Many independent graphs of uneven size, packed back to back in graph-id
  * order: graph g's W, M, idx (and G, dW) occupy n_g^2 elements starting at

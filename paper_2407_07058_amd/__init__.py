@@ -43,6 +43,7 @@ SIGNATURES = {
     "appd_forward_ex": ([_P, _I, _I, _P, _P, _P, _P, _P, _SZ, _P], _I),
     "appd_tree": ([_P, _I, _I, _P, _P, _P, _SZ, _P], _I),
     "appd_fill": ([_I, _I, _P, _SZ, _P, _P, _P], _I),
+    "appd_linkage": ([_P, _I, _I, _P, _P, _SZ, _P], _I),
     "appd_batch_workspace_bytes": ([_P, _I], _SZ),
     "appd_batch_prepare": ([_P, _I, _P, _SZ, _P, _P], _I),
     "appd_forward_batched": ([_P, _I, _P, _P, _P, _P, _P, _P], _I),
@@ -170,6 +171,21 @@ def forward(W: torch.Tensor, mode: int = MINIMAX, return_tree: bool = False, out
     if return_tree:
         return M, idx, order, parent
     return M, idx
+
+
+def linkage(W: torch.Tensor, mode: int = MINIMAX, tree: str = "auto",
+            workspace: torch.Tensor = None) -> torch.Tensor:
+    """Single-linkage dendrogram of one graph: (n-1) x 4 float64 rows
+    (cluster a < b, weight, size); ids >= n are earlier merges."""
+    n = _check_square(W)
+    mode = _mode(mode, tree)
+    Z = torch.empty((max(n - 1, 0), 4), dtype=torch.float64, device=W.device)
+    if workspace is None:
+        workspace = torch.empty(workspace_bytes(n), dtype=torch.uint8, device=W.device)
+    _check(lib().appd_linkage(_ptr(W), n, int(mode), _ptr(Z) if n > 1 else None,
+                              _ptr(workspace), workspace.numel(), _stream(W.device)),
+           "appd_linkage")
+    return Z
 
 
 def tree(W: torch.Tensor, workspace: torch.Tensor, mode: int = MINIMAX, tree: str = "auto"):

@@ -2,6 +2,7 @@
 // error reporting.  All compute is enqueued by the kernels' launchers.
 #include "appd.h"
 #include "appd_internal.h"
+#include "appd_prim.h"
 
 namespace {
 
@@ -103,6 +104,24 @@ int appd_fill(int n, int mode, const void* ws, size_t ws_bytes, float* M, int32_
     if (ws_bytes < appd::single_workspace_bytes(n) || ((uintptr_t)ws & 255u)) return fail(APPD_EINVAL);
     appd::SingleWs w = appd::carve_single(const_cast<void*>(ws), n);
     if (appd::run_fill(n, mode, M, idx, w, (hipStream_t)stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(APPD_EHIP);
+    }
+    return ok();
+}
+
+int appd_linkage(const float* W, int n, int mode, double* Z, void* ws, size_t ws_bytes,
+                 void* stream) {
+    if (bad_n(n) || !W || (!Z && n > 1) || !ws || !appd::valid_mode(mode))
+        return fail(APPD_EINVAL);
+    if (ws_bytes < appd::single_workspace_bytes(n) || ((uintptr_t)ws & 255u)) return fail(APPD_EINVAL);
+    appd::SingleWs w = appd::carve_single(ws, n);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = appd::run_tree(W, n, mode, w, s);
+    if (e == hipSuccess)
+        e = appd::run_linkage(W, n, mode, appd::PrimOut{w.order, w.ek, w.pos, w.parent}, w.tree_ws,
+                              Z, s);
+    if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(APPD_EHIP);
     }

@@ -40,6 +40,8 @@ size_t tree_workspace_bytes(int n);
 struct PrimOut;
 hipError_t run_tree_parallel(const float* W, int n, int mode, const PrimOut& out, void* tws,
                              hipStream_t s);
+hipError_t run_linkage(const float* W, int n, int mode, const PrimOut& out, void* tws, double* Z,
+                       hipStream_t s);
 bool valid_mode(int mode);
 
 size_t single_workspace_bytes(int n);

@@ -1229,4 +1229,138 @@ hipError_t run_tree_parallel(const float* W, int n, int mode, const PrimOut& out
                       : run_tree_parallel_t<false>(W, n, out, tws, s);
 }
 
+// ---------------------------------------------------------------- dendrogram
+// The single-linkage merge table of a graph from Prim's attachment order.  With
+// v_0 .. v_{n-1} the attachment order and h[k] the key of the edge that
+// attached v_k, the pair (v_a, v_b), a < b, merges at max h[a+1..b] (the
+// range-maximum form of Algorithm 4, see appd_fill.h), so the dendrogram is
+// the max-Cartesian tree of h[1..n-1]: node k joins the vertex ranges
+// [pg(k), k-1] and [k, ng(k)-1], pg / ng being the nearest positions with a
+// larger key to the left (0 if none) and to the right (n if none).  From the
+// link tree: pg(k) = pos(link(v_k)), because the vertices between a link
+// parent and v_k hang below it through smaller keys, and ng(k) = k + size(v_k),
+// the end of v_k's link subtree.  A node's parent is whichever of pg, ng holds
+// the smaller key; merge j is the node with the j-th smallest key (the tree
+// order).  Merge rows follow the usual linkage-matrix layout.
+namespace {
+
+__global__ void lk_flag_kernel(int32_t* ctrl) { ctrl[C_ORDERED] = 1; }
+
+__global__ __launch_bounds__(256) void lk_ranges_kernel(int n, const int32_t* order,
+                                                        const int32_t* pos, const int32_t* link,
+                                                        const int32_t* size, int32_t* pg,
+                                                        int32_t* ng, int32_t* lc, int32_t* rc) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (k >= n) return;
+    const int v = order[k];
+    const int l = link[v];
+    pg[k] = l > 0 ? pos[l] : 0;
+    ng[k] = k + size[v];
+    lc[k] = -1;
+    rc[k] = -1;
+}
+
+__global__ __launch_bounds__(256) void lk_children_kernel(int n, const uint64_t* ek,
+                                                          const int32_t* pg, const int32_t* ng,
+                                                          int32_t* lc, int32_t* rc) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (k >= n) return;
+    const int a = pg[k], b = ng[k];
+    int p = -1;
+    if (a >= 1 && b <= n - 1) p = ek[a] < ek[b] ? a : b;
+    else if (a >= 1) p = a;
+    else if (b <= n - 1) p = b;
+    if (p < 0) return;  // the largest key: the root of the dendrogram
+    if (k < p) lc[p] = k;
+    else rc[p] = k;
+}
+
+// rank[k] = number of keys among h[1..n-1] below h[k] (all distinct)
+__global__ __launch_bounds__(256) void lk_rank_kernel(int n, const uint64_t* ek, int32_t* rank) {
+    __shared__ uint64_t tile[256];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    const uint64_t key = k < n ? ek[k] : kNone;
+    int cnt = 0;
+    for (int base = 1; base < n; base += 256) {
+        const int j = base + threadIdx.x;
+        tile[threadIdx.x] = j < n ? ek[j] : kNone;
+        __syncthreads();
+        const int lim = min(256, n - base);
+        for (int q = 0; q < lim; ++q) cnt += tile[q] < key ? 1 : 0;
+        __syncthreads();
+    }
+    if (k < n) rank[k] = cnt;
+}
+
+template <bool WIDEST>
+__global__ __launch_bounds__(256) void lk_rows_kernel(int n, const int32_t* order,
+                                                      const uint64_t* ek, const int32_t* pg,
+                                                      const int32_t* ng, const int32_t* lc,
+                                                      const int32_t* rc, const int32_t* rank,
+                                                      double* Z) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (k >= n) return;
+    const int64_t a = lc[k] >= 0 ? (int64_t)n + rank[lc[k]] : order[k - 1];
+    const int64_t b = rc[k] >= 0 ? (int64_t)n + rank[rc[k]] : order[k];
+    double* z = Z + 4 * (size_t)rank[k];
+    z[0] = (double)(a < b ? a : b);
+    z[1] = (double)(a < b ? b : a);
+    z[2] = (double)key_weight<WIDEST>(ek[k]);
+    z[3] = (double)(ng[k] - pg[k]);
+}
+
+}  // namespace
+
+hipError_t run_linkage(const float* W, int n, int mode, const PrimOut& out, void* tws, double* Z,
+                       hipStream_t s) {
+    if (n < 2) return hipSuccess;
+    TreeWs w = carve_tree(tws, n);
+    const int nb = (n + 255) / 256;
+    const bool widest = (mode & 1) != 0;
+    hipError_t e;
+#define APPD_CHK_L()                                   \
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // link tree and its subtree sizes (from the parent array either tree path
+    // leaves), then the Cartesian-tree structure and the merge order
+    APPD_LAUNCH("lk_flag_kernel", s, lk_flag_kernel<<<1, 1, 0, s>>>(w.ctrl));
+    APPD_CHK_L();
+    if (widest)
+        APPD_LAUNCH("tree_keyup_kernel", s,
+            tree_keyup_kernel<true><<<nb, 256, 0, s>>>(W, n, out.parent, w.keyup, w.link, w.size,
+                w.gcount, w.hook, w.ctrl));
+    else
+        APPD_LAUNCH("tree_keyup_kernel", s,
+            tree_keyup_kernel<false><<<nb, 256, 0, s>>>(W, n, out.parent, w.keyup, w.link, w.size,
+                w.gcount, w.hook, w.ctrl));
+    APPD_CHK_L();
+    APPD_LAUNCH("tree_link_kernel", s,
+        tree_link_kernel<<<nb, 256, 0, s>>>(n, w.keyup, w.link, w.gcount, w.ctrl));
+    APPD_CHK_L();
+    APPD_LAUNCH("tree_sizes_kernel", s,
+        tree_sizes_kernel<<<nb, 256, 0, s>>>(n, w.link, w.size, w.gcount, w.hook, w.ctrl));
+    APPD_CHK_L();
+    // pg, ng, children, rank in arrays the tree no longer needs
+    int32_t *pg = w.gstart, *ng = w.gfill, *lc = w.hx, *rc = w.hy, *rank = w.comp;
+    APPD_LAUNCH("lk_ranges_kernel", s,
+        lk_ranges_kernel<<<nb, 256, 0, s>>>(n, out.order, out.pos, w.link, w.size, pg, ng, lc,
+            rc));
+    APPD_CHK_L();
+    APPD_LAUNCH("lk_children_kernel", s,
+        lk_children_kernel<<<nb, 256, 0, s>>>(n, out.ek, pg, ng, lc, rc));
+    APPD_CHK_L();
+    APPD_LAUNCH("lk_rank_kernel", s, lk_rank_kernel<<<nb, 256, 0, s>>>(n, out.ek, rank));
+    APPD_CHK_L();
+    if (widest)
+        APPD_LAUNCH("lk_rows_kernel", s,
+            lk_rows_kernel<true><<<nb, 256, 0, s>>>(n, out.order, out.ek, pg, ng, lc, rc, rank,
+                Z));
+    else
+        APPD_LAUNCH("lk_rows_kernel", s,
+            lk_rows_kernel<false><<<nb, 256, 0, s>>>(n, out.order, out.ek, pg, ng, lc, rc, rank,
+                Z));
+    APPD_CHK_L();
+#undef APPD_CHK_L
+    return hipSuccess;
+}
+
 }  // namespace appd

@@ -137,7 +137,27 @@ def bench_single(appd, torch, W, n, steps, warmup):
     ms = elapsed(t0, t1) / steps
     assert not overflow and launches > 0
     avg_launch_ms = kern_ms / launches
-    return Wd, ms, census, dominant, launches / steps, avg_launch_ms
+
+    # the same forward captured once in a HIP graph and replayed (the call only
+    # launches kernels when given a workspace)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    graph.replay()
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        graph.replay()
+    t1.record()
+    torch.cuda.synchronize()
+    graph_ms = elapsed(t0, t1) / steps
+    return Wd, ms, census, dominant, launches / steps, avg_launch_ms, graph_ms
 
 
 def bench_batched(appd, torch, steps):
@@ -356,8 +376,8 @@ def main():
         wl = "single complete graph, n=%d points from the 10-component mixture (seed 2)" % n
     wl_key = "single-%d" % n
     print("step single-graph forward n=%d" % n, file=sys.stderr, flush=True)
-    Wd, ms, census, dom, dom_launches, dom_ms = bench_single(appd, torch, W, n, args.steps,
-                                                            args.warmup)
+    Wd, ms, census, dom, dom_launches, dom_ms, graph_ms = bench_single(appd, torch, W, n,
+                                                                      args.steps, args.warmup)
     del Wd
     torch.cuda.empty_cache()
 
@@ -387,6 +407,8 @@ def main():
         "config": {"workload": wl, "n": n, "mode": "minimax"},
         "alg_hbm_gbps": 12.0 * entries / (ms / 1e3) / 1e9,
         "alg_hbm_frac": 12.0 * entries / (ms / 1e3) / 1e9 / HBM_PEAK_GBPS,
+        "graph_replay_ms_per_step": graph_ms,
+        "graph_replay_value": entries / (graph_ms / 1e3),
         "kernels": census,
         "roofline": roofline,
     }

@@ -50,6 +50,9 @@ constexpr uint16_t kNoId = 0xffff;  // end of a short list (n < 65535 always)
 // the waves of the rounds kernel, whose lanes hold consecutive vertices, read
 // contiguous memory.  The edge key of an entry is ord32 << 32 | flat(u, id).
 constexpr int kGroupWords = 8;
+#ifndef APPD_WALK_GROUPS
+#define APPD_WALK_GROUPS 2
+#endif
 
 // control block (int32 words); word 32 holds the number of rank tiles
 enum { C_DONE = 0, C_NCOMP, C_NEED_PASS, C_FALLBACK, C_ROUNDS, C_ORDERED, C_WORDS };
@@ -440,6 +443,7 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
     //    another round on the same lists.  A wave whose vertices share one
     //    component sends one atomic per minimum.
     constexpr int kW = 8;  // vertices per thread
+    constexpr int kWalkGroups = APPD_WALK_GROUPS;  // list groups a vertex may read per round
     constexpr int kStride = kW * kRoundThreads;
     constexpr int GW = kGroupWords;
     for (int guard = 0; guard < 128 && !ctrl[C_DONE]; ++guard) {
@@ -467,55 +471,96 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
                 }
             }
             int npend = 0;
+            int cuv[kW];
+            uint64_t key[kW];
+            uint32_t walk = 0, isb = 0, pendm = 0, moved = 0;  // bit i: vertex i
 #pragma unroll
             for (int i = 0; i < kW; ++i) {
                 const int u = base + i * kRoundThreads + t;
-                const bool act = u < n;
-                const int cu = act ? getc(u) : -1;
-                uint64_t kc = kNone, kb = kNone;
-                bool pend = false;
-                if (act) {
+                cuv[i] = u < n ? getc(u) : -1;
+                key[i] = kNone;
+                if (u < n) walk |= 1u << i;
+            }
+            for (int step = 0; step < kWalkGroups; ++step) {
+                uint32_t next = 0;
+#pragma unroll
+                for (int i = 0; i < kW; ++i) {
+                    if (!((walk >> i) & 1u)) continue;
+                    const int u = base + i * kRoundThreads + t;
                     const uint32_t id4[4] = {gr[i].x & 0xffffu, gr[i].x >> 16, gr[i].y & 0xffffu,
                                              gr[i].y >> 16};
                     const uint32_t od4[4] = {gr[i].z, gr[i].w, go[i].x, go[i].y};
                     const int p = pp[i];
+                    walk &= ~(1u << i);
                     if (p >= kK) {  // exhausted in an earlier round
-                        if (id4[3] != kNoId) kb = ((uint64_t)od4[3] << 32) | flat_idx(u, id4[3], n);
-                    } else {
-                        const int q = p & ~3;
-                        int found = -1;
-                        bool shortl = false;
-#pragma unroll
-                        for (int r = 3; r >= 0; --r) {  // the first qualifying entry wins
-                            if (q + r < p) continue;
-                            if (id4[r] == kNoId) {
-                                shortl = true;
-                                found = -1;
-                            } else if (getc((int)id4[r]) != cu) {
-                                found = r;
-                                shortl = false;
-                            }
+                        if (id4[3] != kNoId) {
+                            key[i] = ((uint64_t)od4[3] << 32) | flat_idx(u, id4[3], n);
+                            isb |= 1u << i;
                         }
-                        int np;
-                        if (found >= 0) {
-                            uint32_t v = id4[0], o = od4[0];
+                        continue;
+                    }
+                    const int q = p & ~3;
+                    int found = -1;
+                    bool shortl = false;
 #pragma unroll
-                            for (int r = 1; r < 4; ++r) {
-                                v = found == r ? id4[r] : v;
-                                o = found == r ? od4[r] : o;
-                            }
-                            kc = ((uint64_t)o << 32) | flat_idx(u, v, n);
-                            np = q + found;
-                        } else if (shortl) {
-                            np = kK;  // nothing beyond a short list: no bound
-                        } else {      // rest of the group internal: its last entry bounds
-                            kb = ((uint64_t)od4[3] << 32) | flat_idx(u, id4[3], n);
-                            np = q + 4;
-                            pend = np < kK;
+                    for (int r = 3; r >= 0; --r) {  // the first qualifying entry wins
+                        if (q + r < p) continue;
+                        if (id4[r] == kNoId) {
+                            shortl = true;
+                            found = -1;
+                        } else if (getc((int)id4[r]) != cuv[i]) {
+                            found = r;
+                            shortl = false;
                         }
-                        if (np != p) a.lptr[u] = np;
+                    }
+                    if (found >= 0) {
+                        uint32_t v = id4[0], o = od4[0];
+#pragma unroll
+                        for (int r = 1; r < 4; ++r) {
+                            v = found == r ? id4[r] : v;
+                            o = found == r ? od4[r] : o;
+                        }
+                        key[i] = ((uint64_t)o << 32) | flat_idx(u, v, n);
+                        isb &= ~(1u << i);
+                        if (q + found != p) moved |= 1u << i;
+                        pp[i] = q + found;
+                    } else if (shortl) {
+                        key[i] = kNone;  // nothing beyond a short list: no bound
+                        isb &= ~(1u << i);
+                        pp[i] = kK;
+                        moved |= 1u << i;
+                    } else {  // rest of the group internal: its last entry bounds
+                        key[i] = ((uint64_t)od4[3] << 32) | flat_idx(u, id4[3], n);
+                        isb |= 1u << i;
+                        pp[i] = q + 4;
+                        moved |= 1u << i;
+                        if (pp[i] < kK) {
+                            if (step + 1 < kWalkGroups) next |= 1u << i;
+                            else pendm |= 1u << i;
+                        }
                     }
                 }
+                if (!next) break;
+#pragma unroll
+                for (int i = 0; i < kW; ++i) {
+                    if (!((next >> i) & 1u)) continue;
+                    const int u = base + i * kRoundThreads + t;
+                    const uint32_t* G = a.groups + ((size_t)(pp[i] >> 2) * n + u) * GW;
+                    gr[i] = *(const uint4*)G;
+                    go[i] = *(const uint2*)(G + 4);
+                }
+                walk = next;
+            }
+#pragma unroll
+            for (int i = 0; i < kW; ++i) {
+                const int u = base + i * kRoundThreads + t;
+                const bool act = u < n;
+                const int cu = cuv[i];
+                const bool isbi = (isb >> i) & 1u;
+                const uint64_t kc = isbi ? kNone : key[i];
+                const uint64_t kb = isbi ? key[i] : kNone;
+                const bool pend = (pendm >> i) & 1u;
+                if (act && ((moved >> i) & 1u)) a.lptr[u] = pp[i];
                 npend += __popcll(__ballot(pend));
                 const int c0 = __builtin_amdgcn_readfirstlane(cu);
                 const uint64_t same = __ballot(act && cu == c0);

@@ -157,6 +157,38 @@ __device__ __forceinline__ uint64_t wave_excl_max_down(uint64_t x, int lane) {
     return (lane & 15) == 15 ? carry : umax64(next, carry);
 }
 
+// 32-bit forms of the scans above (one DPP move per step).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x, uint32_t fill) {
+    return __builtin_amdgcn_update_dpp((int)fill, (int)x, CTRL, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t wave_excl_max_up_u32(uint32_t x, int lane) {
+    x = max(x, dpp_u32<0x111>(x, 0));
+    x = max(x, dpp_u32<0x112>(x, 0));
+    x = max(x, dpp_u32<0x114>(x, 0));
+    x = max(x, dpp_u32<0x118>(x, 0));
+    const uint32_t r0 = __builtin_amdgcn_readlane(x, 15), r1 = __builtin_amdgcn_readlane(x, 31),
+                   r2 = __builtin_amdgcn_readlane(x, 47);
+    const int row = lane >> 4;
+    const uint32_t carry = row == 0 ? 0u : row == 1 ? r0 : row == 2 ? max(r0, r1) : max(max(r0, r1), r2);
+    const uint32_t prev = dpp_u32<0x111>(x, 0);
+    return (lane & 15) == 0 ? carry : max(prev, carry);
+}
+
+__device__ __forceinline__ uint32_t wave_excl_max_down_u32(uint32_t x, int lane) {
+    x = max(x, dpp_u32<0x101>(x, 0));
+    x = max(x, dpp_u32<0x102>(x, 0));
+    x = max(x, dpp_u32<0x104>(x, 0));
+    x = max(x, dpp_u32<0x108>(x, 0));
+    const uint32_t h1 = __builtin_amdgcn_readlane(x, 16), h2 = __builtin_amdgcn_readlane(x, 32),
+                   h3 = __builtin_amdgcn_readlane(x, 48);
+    const int row = lane >> 4;
+    const uint32_t carry = row == 3 ? 0u : row == 2 ? h3 : row == 1 ? max(h2, h3) : max(max(h1, h2), h3);
+    const uint32_t next = dpp_u32<0x101>(x, 0);
+    return (lane & 15) == 15 ? carry : max(next, carry);
+}
+
 // Orders LDS traffic of one wave: writes before the fence are visible to reads
 // of other lanes of the same wave after it.
 __device__ __forceinline__ void wave_lds_sync() {

@@ -39,14 +39,29 @@ namespace appd {
 // belongs to slot k = the number of sorted positions below p, read off a bitmap
 // of those positions and its per-word prefix counts, and is folded into gap[k]
 // with an LDS atomic max.  ek is read coalesced, once per block.
-// LDS: keys CB words; bits and prefix (n + 31) / 32 words each; gap CB keys.
-template <int CB>
+// Then the block's gap keys are sorted (bitonic, u64) and every slot k >= 1
+// gets its code for the fill: (2 * (rank of gap[k] among the block's gaps + 1))
+// << 11 | k, an order-preserving 32-bit stand-in for the key, together with the
+// decoded weight and flat index of gap[k] (decode tables indexed by k; entry 0
+// is the diagonal: 0.0, -1).  The sorted gaps are kept so that the fill can
+// code the two boundary keys of a row the same way.
+// LDS: keys CB words; bits and prefix (n + 31) / 32 words each; gap and srt CB
+// keys each.
+constexpr int kCodeShift = 11;  // slot codes below 2^11 (CB + boundary entries)
+constexpr uint32_t kCodeMask = (1u << kCodeShift) - 1;
+
+template <int CB, bool WIDEST>
 __device__ __forceinline__ void fill_prep_block(const int32_t* __restrict__ pos,
                                                 const uint64_t* __restrict__ ek, int n, int blk,
                                                 uint16_t* __restrict__ blk_sp,
                                                 uint16_t* __restrict__ blk_slot,
-                                                uint64_t* __restrict__ blk_gap, uint32_t* keys,
-                                                uint32_t* bits, int32_t* wpre, uint64_t* gap) {
+                                                uint32_t* __restrict__ blk_code,
+                                                float* __restrict__ blk_dM,
+                                                int32_t* __restrict__ blk_dI,
+                                                uint64_t* __restrict__ blk_sorted, uint32_t* keys,
+                                                uint32_t* bits, int32_t* wpre, uint64_t* gap,
+                                                uint64_t* srt) {
+    static_assert(CB + 16 <= (1 << kCodeShift), "slot codes must fit");
     const int j0 = blk * CB;
     const int cnt = min(CB, n - j0);
     const int nw = (n + 31) / 32;
@@ -109,7 +124,45 @@ __device__ __forceinline__ void fill_prep_block(const int32_t* __restrict__ pos,
         atomicMax((unsigned long long*)&gap[k], (unsigned long long)ek[p]);
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < cnt; k += blockDim.x) blk_gap[j0 + k] = gap[k];
+    // sorted gaps (slots 1..cnt-1), padded with the largest key
+    for (int k = threadIdx.x; k < CB; k += blockDim.x) srt[k] = (k + 1 < cnt) ? gap[k + 1] : ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= CB; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < CB / 2; i += blockDim.x) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                const uint64_t x = srt[lo], y = srt[hi];
+                if ((x > y) == asc) {
+                    srt[lo] = y;
+                    srt[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+        uint32_t code = 0;
+        float dm = 0.0f;
+        int32_t di = -1;
+        if (k > 0) {
+            const uint64_t key = gap[k];
+            int lo = 0, hi = cnt - 1;  // rank of key among srt[0 .. cnt-2]
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (srt[mid] < key) lo = mid + 1;
+                else hi = mid;
+            }
+            code = ((uint32_t)(2 * (lo + 1)) << kCodeShift) | (uint32_t)k;
+            dm = key_weight<WIDEST>(key);
+            di = (int32_t)(uint32_t)key;
+        }
+        blk_code[j0 + k] = code;
+        blk_dM[j0 + k] = dm;
+        blk_dI[j0 + k] = di;
+        blk_sorted[j0 + k] = srt[k];
+    }
 }
 
 // One column block, rows [r0, r1), waves of the workgroup take rows in turn.
@@ -224,6 +277,131 @@ __device__ __forceinline__ void fill_rows_block(const int32_t* __restrict__ pos,
                 const uint64_t key = s_R[s_slot[c]];
                 mrow[c] = key ? key_weight<WIDEST>(key) : 0.0f;
                 irow[c] = key ? (int32_t)(uint32_t)key : -1;
+            }
+        }
+        wave_lds_sync();
+    }
+}
+
+// The same fill on 32-bit slot codes (fill_prep_block): the running maxima
+// are taken over codes, which order like the keys, and each output is decoded
+// through the block's tables in LDS.  The two boundary keys of a row (not gap
+// values) are coded between the gaps by a binary search in the sorted gaps,
+// with per-wave decode entries at CB + 2 * wave (left) and CB + 2 * wave + 1
+// (right).  s_R: this wave's row buffer of CB codes; s_dM / s_dI: CB + 2 *
+// nwaves entries.
+template <int CB, bool WIDEST, bool VEC>
+__device__ __forceinline__ void fill_rows_block_coded(
+    const int32_t* __restrict__ pos, const uint64_t* __restrict__ ek, int n, int j0, int cnt,
+    int r0, int r1, const uint16_t* s_sp, const uint16_t* s_slot, const uint32_t* s_code,
+    const uint64_t* s_sorted, float* s_dM, int32_t* s_dI, uint32_t* s_R, float* __restrict__ M,
+    int32_t* __restrict__ idx, int nwaves) {
+    constexpr int S = CB / kWave;
+    static_assert(S >= 1 && S <= kWave, "CB must be in [64, 4096]");
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int k0 = lane * S;
+    uint32_t g[S];  // codes of slots k0 + q; padding slots hold 0
+#pragma unroll
+    for (int q = 0; q < S; ++q) g[q] = s_code[k0 + q];
+    uint32_t gnx = __shfl_down(g[0], 1);  // code of slot k0 + S
+    if (lane == kWave - 1) gnx = 0;
+    const int sp_last = s_sp[k0 + S - 1];  // padded slots hold 0xffff
+    const uint32_t cl = (uint32_t)(CB + 2 * wid), cr = cl + 1;
+    auto code_of = [&](uint64_t key, uint32_t slot) -> uint32_t {
+        int lo = 0, hi = cnt - 1;  // gaps below key among s_sorted[0 .. cnt-2]
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_sorted[mid] < key) lo = mid + 1;
+            else hi = mid;
+        }
+        return ((uint32_t)(2 * lo + 1) << kCodeShift) | slot;
+    };
+
+    int i = r0 + wid;
+    int a_next = i < r1 ? pos[i] : 0;
+    for (; i < r1; i += nwaves) {
+        const int a = a_next;
+        if (i + nwaves < r1) a_next = pos[i + nwaves];
+        // k* = number of slots whose position is below a
+        const int nbl = __popcll(__ballot(sp_last < a));
+        const int base = nbl * S;
+        const bool part = (lane < S) && (base + lane < CB) && (s_sp[min(base + lane, CB - 1)] < a);
+        const int ks = base + __popcll(__ballot(part));
+        const bool diag = ks < cnt && (int)s_sp[ks] == a;
+
+        // codes of the keys crossed next to the row's own position
+        uint32_t bl = 0, br = 0;
+        if (diag) {
+            bl = ks > 0 ? s_code[ks] : 0u;
+        } else {
+            const int lo = ks > 0 ? (int)s_sp[ks - 1] + 1 : a + 1;
+            const int hi = ks < cnt ? (int)s_sp[ks] : a;
+            uint64_t kl = 0, kr = 0;
+            for (int x = lo + lane; x <= hi; x += kWave) {
+                const uint64_t e = ek[x];
+                if (x <= a) kl = umax64(kl, e);
+                else kr = umax64(kr, e);
+            }
+            kl = wave_max_u64(kl);
+            kr = wave_max_u64(kr);
+            if (kl) bl = code_of(kl, cl);
+            if (kr) br = code_of(kr, cr);
+            if (lane == 0) {
+                s_dM[cl] = kl ? key_weight<WIDEST>(kl) : 0.0f;
+                s_dI[cl] = kl ? (int32_t)(uint32_t)kl : -1;
+                s_dM[cr] = kr ? key_weight<WIDEST>(kr) : 0.0f;
+                s_dI[cr] = kr ? (int32_t)(uint32_t)kr : -1;
+            }
+        }
+
+        // lane-local running maxima: upward over slots >= k*, downward below
+        uint32_t loc[S];
+        uint32_t run = 0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int k = k0 + q;
+            const uint32_t e = k > ks ? g[q] : (k == ks ? br : 0u);
+            run = max(run, e);
+            loc[q] = run;
+        }
+        const uint32_t up_tot = run;
+        run = 0;
+#pragma unroll
+        for (int q = S - 1; q >= 0; --q) {
+            const int k = k0 + q;
+            const uint32_t nxt = q + 1 < S ? g[q + 1] : gnx;
+            const uint32_t e = k < ks - 1 ? nxt : (k == ks - 1 ? bl : 0u);
+            run = max(run, e);
+            if (k < ks) loc[q] = run;
+        }
+        const uint32_t dn_tot = run;
+        const uint32_t up_in = wave_excl_max_up_u32(up_tot, lane);
+        const uint32_t dn_in = wave_excl_max_down_u32(dn_tot, lane);
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int k = k0 + q;
+            s_R[k] = max(loc[q], k >= ks ? up_in : dn_in);
+        }
+        wave_lds_sync();
+
+        float* mrow = M + (size_t)i * (size_t)n + j0;
+        int32_t* irow = idx + (size_t)i * (size_t)n + j0;
+        if (VEC) {
+            for (int c = lane * 4; c < cnt; c += kWave * 4) {
+                const uint64_t sl = *(const uint64_t*)(s_slot + c);  // 4 slots
+                const uint32_t c0 = s_R[sl & 0xffff] & kCodeMask;
+                const uint32_t c1 = s_R[(sl >> 16) & 0xffff] & kCodeMask;
+                const uint32_t c2 = s_R[(sl >> 32) & 0xffff] & kCodeMask;
+                const uint32_t c3 = s_R[sl >> 48] & kCodeMask;
+                *(float4*)(mrow + c) = make_float4(s_dM[c0], s_dM[c1], s_dM[c2], s_dM[c3]);
+                *(int4*)(irow + c) = make_int4(s_dI[c0], s_dI[c1], s_dI[c2], s_dI[c3]);
+            }
+        } else {
+            for (int c = lane; c < cnt; c += kWave) {
+                const uint32_t cd = s_R[s_slot[c]] & kCodeMask;
+                mrow[c] = s_dM[cd];
+                irow[c] = s_dI[cd];
             }
         }
         wave_lds_sync();

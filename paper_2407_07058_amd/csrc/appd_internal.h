@@ -30,9 +30,12 @@ struct SingleWs {
     int32_t* parent;
     int32_t* pos;
     uint64_t* ek;
-    uint16_t* blk_sp;
-    uint16_t* blk_slot;
-    uint64_t* blk_gap;
+    uint16_t* blk_sp;     // per column block: attachment positions of the columns, sorted
+    uint16_t* blk_slot;   // slot of each column in that order
+    uint32_t* blk_code;   // slot codes (order-preserving stand-ins for the gap keys)
+    float* blk_dM;        // decoded weight of each slot's gap key (entry 0: diagonal)
+    int32_t* blk_dI;      // decoded flat index of each slot's gap key
+    uint64_t* blk_sorted; // the block's gap keys in ascending order
     void* tree_ws;  // scratch of the parallel tree
 };
 

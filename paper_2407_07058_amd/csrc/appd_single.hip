@@ -19,43 +19,50 @@ __global__ __launch_bounds__(kPrimThreads) void prim_single_kernel(const float* 
     prim_run<kPrimThreads, CH, WIDEST>(W, n, out, red_key, red_v);
 }
 
-template <int CB>
+template <int CB, bool WIDEST>
 __global__ __launch_bounds__(kFillThreads) void fill_prep_kernel(const int32_t* __restrict__ pos,
                                                                  const uint64_t* __restrict__ ek,
-                                                                 int n, uint16_t* blk_sp,
-                                                                 uint16_t* blk_slot,
-                                                                 uint64_t* blk_gap) {
+                                                                 int n, SingleWs w) {
     __shared__ uint32_t keys[CB];
     __shared__ uint32_t bits[(APPD_MAX_N + 31) / 32];
     __shared__ int32_t wpre[(APPD_MAX_N + 31) / 32];
     __shared__ uint64_t gap[CB];
-    fill_prep_block<CB>(pos, ek, n, blockIdx.x, blk_sp, blk_slot, blk_gap, keys, bits, wpre, gap);
+    __shared__ uint64_t srt[CB];
+    fill_prep_block<CB, WIDEST>(pos, ek, n, blockIdx.x, w.blk_sp, w.blk_slot, w.blk_code, w.blk_dM,
+                                w.blk_dI, w.blk_sorted, keys, bits, wpre, gap, srt);
 }
 
 template <int CB, bool WIDEST, bool VEC>
-__global__ __launch_bounds__(kFillThreads) void fill_kernel(
-    const int32_t* __restrict__ pos, const uint64_t* __restrict__ ek, int n,
-    const uint16_t* __restrict__ blk_sp, const uint16_t* __restrict__ blk_slot,
-    const uint64_t* __restrict__ blk_gap, float* __restrict__ M, int32_t* __restrict__ idx,
-    int rows_per_wg) {
+__global__ __launch_bounds__(kFillThreads) void fill_kernel(const int32_t* __restrict__ pos,
+                                                            const uint64_t* __restrict__ ek, int n,
+                                                            SingleWs w, float* __restrict__ M,
+                                                            int32_t* __restrict__ idx,
+                                                            int rows_per_wg) {
     constexpr int NWV = kFillThreads / kWave;
     __shared__ uint16_t s_sp[CB];
     __shared__ __align__(16) uint16_t s_slot[CB];
-    __shared__ uint64_t s_gap[CB];
-    __shared__ uint64_t s_R[NWV][CB];
+    __shared__ uint32_t s_code[CB];
+    __shared__ uint64_t s_sorted[CB];
+    __shared__ float s_dM[CB + 2 * NWV];
+    __shared__ int32_t s_dI[CB + 2 * NWV];
+    __shared__ uint32_t s_R[NWV][CB];
     const int j0 = blockIdx.x * CB;
     const int cnt = min(CB, n - j0);
     for (int k = threadIdx.x; k < CB; k += kFillThreads) {
         const bool in = k < cnt;
-        s_sp[k] = in ? blk_sp[j0 + k] : (uint16_t)0xffff;
-        s_slot[k] = in ? blk_slot[j0 + k] : (uint16_t)0;
-        s_gap[k] = in ? blk_gap[j0 + k] : 0ull;
+        s_sp[k] = in ? w.blk_sp[j0 + k] : (uint16_t)0xffff;
+        s_slot[k] = in ? w.blk_slot[j0 + k] : (uint16_t)0;
+        s_code[k] = in ? w.blk_code[j0 + k] : 0u;
+        s_sorted[k] = in ? w.blk_sorted[j0 + k] : ~0ull;
+        s_dM[k] = in ? w.blk_dM[j0 + k] : 0.0f;
+        s_dI[k] = in ? w.blk_dI[j0 + k] : -1;
     }
     __syncthreads();
     const int r0 = blockIdx.y * rows_per_wg;
     const int r1 = min(n, r0 + rows_per_wg);
-    fill_rows_block<CB, WIDEST, VEC>(pos, ek, n, j0, cnt, r0, r1, s_sp, s_slot, s_gap,
-                                     s_R[threadIdx.x / kWave], M, idx, NWV);
+    fill_rows_block_coded<CB, WIDEST, VEC>(pos, ek, n, j0, cnt, r0, r1, s_sp, s_slot, s_code,
+                                           s_sorted, s_dM, s_dI, s_R[threadIdx.x / kWave], M, idx,
+                                           NWV);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -91,7 +98,10 @@ size_t single_workspace_bytes(int n) {
     off = align_up(off + 8 * (size_t)n);  // ek
     off = align_up(off + 2 * nb);         // blk_sp
     off = align_up(off + 2 * nb);         // blk_slot
-    off = align_up(off + 8 * nb);         // blk_gap
+    off = align_up(off + 4 * nb);         // blk_code
+    off = align_up(off + 4 * nb);         // blk_dM
+    off = align_up(off + 4 * nb);         // blk_dI
+    off = align_up(off + 8 * nb);         // blk_sorted
     off = align_up(off + tree_workspace_bytes(n));
     return off;
 }
@@ -113,7 +123,13 @@ SingleWs carve_single(void* ws, int n) {
     off = align_up(off + 2 * nb);
     w.blk_slot = (uint16_t*)(b + off);
     off = align_up(off + 2 * nb);
-    w.blk_gap = (uint64_t*)(b + off);
+    w.blk_code = (uint32_t*)(b + off);
+    off = align_up(off + 4 * nb);
+    w.blk_dM = (float*)(b + off);
+    off = align_up(off + 4 * nb);
+    w.blk_dI = (int32_t*)(b + off);
+    off = align_up(off + 4 * nb);
+    w.blk_sorted = (uint64_t*)(b + off);
     off = align_up(off + 8 * nb);
     w.tree_ws = b + off;
     return w;
@@ -131,20 +147,19 @@ template <bool WIDEST>
 static hipError_t run_fill_t(int n, float* M, int32_t* idx, const SingleWs& w, hipStream_t s) {
     const int nb = fill_blocks(n);
     APPD_LAUNCH("fill_prep_kernel", s,
-        fill_prep_kernel<kFillCB><<<nb, kFillThreads, 0, s>>>(w.pos, w.ek, n, w.blk_sp, w.blk_slot,
-            w.blk_gap));
+        fill_prep_kernel<kFillCB, WIDEST><<<nb, kFillThreads, 0, s>>>(w.pos, w.ek, n, w));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 grid(nb, (n + kFillRowsPerWG - 1) / kFillRowsPerWG);
     const bool vec = (n % 4 == 0) && (((uintptr_t)M | (uintptr_t)idx) & 15u) == 0;
     if (vec)
         APPD_LAUNCH("fill_kernel", s,
-            fill_kernel<kFillCB, WIDEST, true><<<grid, kFillThreads, 0, s>>>(w.pos, w.ek, n,
-                w.blk_sp, w.blk_slot, w.blk_gap, M, idx, kFillRowsPerWG));
+            fill_kernel<kFillCB, WIDEST, true><<<grid, kFillThreads, 0, s>>>(w.pos, w.ek, n, w, M,
+                idx, kFillRowsPerWG));
     else
         APPD_LAUNCH("fill_kernel", s,
-            fill_kernel<kFillCB, WIDEST, false><<<grid, kFillThreads, 0, s>>>(w.pos, w.ek, n,
-                w.blk_sp, w.blk_slot, w.blk_gap, M, idx, kFillRowsPerWG));
+            fill_kernel<kFillCB, WIDEST, false><<<grid, kFillThreads, 0, s>>>(w.pos, w.ek, n, w, M,
+                idx, kFillRowsPerWG));
     return hipGetLastError();
 }
 

@@ -9,7 +9,7 @@ namespace appd {
 constexpr int kPrimThreads = 1024;
 constexpr int kFillCB = 1024;
 constexpr int kFillThreads = 256;
-constexpr int kFillRowsPerWG = 32;
+constexpr int kFillRowsPerWG = 16;
 
 template <int CH, bool WIDEST>
 __global__ __launch_bounds__(kPrimThreads) void prim_single_kernel(const float* __restrict__ W,

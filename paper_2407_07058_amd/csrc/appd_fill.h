@@ -101,8 +101,9 @@ __device__ __forceinline__ void fill_prep_block(const int32_t* __restrict__ pos,
     const int w0 = min(nw, (int)threadIdx.x * per), w1 = min(nw, w0 + per);
     int c = 0;
     for (int w = w0; w < w1; ++w) c += __popc(bits[w]);
-    // exclusive scan of the threads' counts (Hillis-Steele in LDS)
-    __shared__ int s_cnt[256];
+    // exclusive scan of the threads' counts (Hillis-Steele in LDS; up to 1024
+    // threads)
+    __shared__ int s_cnt[1024];
     s_cnt[threadIdx.x] = c;
     __syncthreads();
     for (int d = 1; d < (int)blockDim.x; d <<= 1) {

@@ -9,6 +9,7 @@ namespace appd {
 constexpr int kPrimThreads = 1024;
 constexpr int kFillCB = 1024;
 constexpr int kFillThreads = 256;
+constexpr int kPrepThreads = 1024;  // one workgroup per column block: sorts and sweeps
 constexpr int kFillRowsPerWG = 16;
 
 template <int CH, bool WIDEST>
@@ -20,7 +21,7 @@ __global__ __launch_bounds__(kPrimThreads) void prim_single_kernel(const float* 
 }
 
 template <int CB, bool WIDEST>
-__global__ __launch_bounds__(kFillThreads) void fill_prep_kernel(const int32_t* __restrict__ pos,
+__global__ __launch_bounds__(kPrepThreads) void fill_prep_kernel(const int32_t* __restrict__ pos,
                                                                  const uint64_t* __restrict__ ek,
                                                                  int n, SingleWs w) {
     __shared__ uint32_t keys[CB];
@@ -147,7 +148,7 @@ template <bool WIDEST>
 static hipError_t run_fill_t(int n, float* M, int32_t* idx, const SingleWs& w, hipStream_t s) {
     const int nb = fill_blocks(n);
     APPD_LAUNCH("fill_prep_kernel", s,
-        fill_prep_kernel<kFillCB, WIDEST><<<nb, kFillThreads, 0, s>>>(w.pos, w.ek, n, w));
+        fill_prep_kernel<kFillCB, WIDEST><<<nb, kPrepThreads, 0, s>>>(w.pos, w.ek, n, w));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 grid(nb, (n + kFillRowsPerWG - 1) / kFillRowsPerWG);

@@ -481,60 +481,51 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
                 key[i] = kNone;
                 if (u < n) walk |= 1u << i;
             }
+            // lists shorter than K (end marked by kNoId) exist only when n <= K
+            const bool shortlists = n <= kK;
             for (int step = 0; step < kWalkGroups; ++step) {
                 uint32_t next = 0;
 #pragma unroll
                 for (int i = 0; i < kW; ++i) {
-                    if (!((walk >> i) & 1u)) continue;
                     const int u = base + i * kRoundThreads + t;
                     const uint32_t id4[4] = {gr[i].x & 0xffffu, gr[i].x >> 16, gr[i].y & 0xffffu,
                                              gr[i].y >> 16};
                     const uint32_t od4[4] = {gr[i].z, gr[i].w, go[i].x, go[i].y};
+                    // bit r: entry q+r leaves the vertex's component (components
+                    // looked up unconditionally: no branch between the LDS reads)
+                    uint32_t ext = 0, nil = 0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const bool ok = id4[r] < (uint32_t)n;
+                        const int c = getc(ok ? (int)id4[r] : 0);
+                        ext |= (ok && c != cuv[i]) ? 1u << r : 0u;
+                        nil |= ok ? 0u : 1u << r;
+                    }
+                    const bool w = (walk >> i) & 1u;
                     const int p = pp[i];
-                    walk &= ~(1u << i);
-                    if (p >= kK) {  // exhausted in an earlier round
-                        if (id4[3] != kNoId) {
-                            key[i] = ((uint64_t)od4[3] << 32) | flat_idx(u, id4[3], n);
-                            isb |= 1u << i;
-                        }
-                        continue;
-                    }
                     const int q = p & ~3;
-                    int found = -1;
-                    bool shortl = false;
+                    // entries at or after the pointer; an exhausted list (p = K,
+                    // last group loaded) only contributes its entry K-1 as a bound
+                    const uint32_t live = p >= kK ? 0u : (0xfu << (p - q)) & 0xfu;
+                    const uint32_t stop = live & (ext | (shortlists ? nil : 0u));
+                    const int first = stop ? __builtin_ctz(stop) : 3;
+                    uint32_t v = id4[0], o = od4[0];
 #pragma unroll
-                    for (int r = 3; r >= 0; --r) {  // the first qualifying entry wins
-                        if (q + r < p) continue;
-                        if (id4[r] == kNoId) {
-                            shortl = true;
-                            found = -1;
-                        } else if (getc((int)id4[r]) != cuv[i]) {
-                            found = r;
-                            shortl = false;
-                        }
+                    for (int r = 1; r < 4; ++r) {
+                        v = first == r ? id4[r] : v;
+                        o = first == r ? od4[r] : o;
                     }
-                    if (found >= 0) {
-                        uint32_t v = id4[0], o = od4[0];
-#pragma unroll
-                        for (int r = 1; r < 4; ++r) {
-                            v = found == r ? id4[r] : v;
-                            o = found == r ? od4[r] : o;
-                        }
-                        key[i] = ((uint64_t)o << 32) | flat_idx(u, v, n);
-                        isb &= ~(1u << i);
-                        if (q + found != p) moved |= 1u << i;
-                        pp[i] = q + found;
-                    } else if (shortl) {
-                        key[i] = kNone;  // nothing beyond a short list: no bound
-                        isb &= ~(1u << i);
-                        pp[i] = kK;
-                        moved |= 1u << i;
-                    } else {  // rest of the group internal: its last entry bounds
-                        key[i] = ((uint64_t)od4[3] << 32) | flat_idx(u, id4[3], n);
-                        isb |= 1u << i;
-                        pp[i] = q + 4;
-                        moved |= 1u << i;
-                        if (pp[i] < kK) {
+                    const bool shortl = shortlists && ((stop & nil) >> first & 1u);
+                    const bool found = stop && !shortl;
+                    const bool bound = !stop && v < (uint32_t)n;  // group internal: entry q+3 bounds
+                    const int np = p >= kK ? kK : (found ? q + first : (shortl ? kK : q + 4));
+                    if (w) {
+                        walk &= ~(1u << i);
+                        key[i] = (found || bound) ? (((uint64_t)o << 32) | flat_idx(u, v, n)) : kNone;
+                        isb = bound ? (isb | (1u << i)) : (isb & ~(1u << i));
+                        if (np != p) moved |= 1u << i;
+                        pp[i] = np;
+                        if (!found && !shortl && np < kK) {
                             if (step + 1 < kWalkGroups) next |= 1u << i;
                             else pendm |= 1u << i;
                         }
@@ -566,10 +557,13 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
                 const uint64_t same = __ballot(act && cu == c0);
                 const uint64_t acts = __ballot(act);
                 if (same == acts) {
-                    const uint64_t mc = wave_min_u64(kc), mb = wave_min_u64(kb);
-                    if (lane == 0) {
-                        if (mc != kNone) min_best(c0, mc);
-                        if (mb != kNone) min_lb(c0, mb);
+                    if (__ballot(kc != kNone)) {
+                        const uint64_t mc = wave_min_u64(kc);
+                        if (lane == 0) min_best(c0, mc);
+                    }
+                    if (__ballot(kb != kNone)) {
+                        const uint64_t mb = wave_min_u64(kb);
+                        if (lane == 0) min_lb(c0, mb);
                     }
                 } else if (act) {
                     if (kc != kNone) min_best(cu, kc);

@@ -45,15 +45,24 @@ KERNEL_SOURCES = {
 }
 
 
-def alg_bytes_per_launch(kernel, n):
-    """Algorithmic HBM bytes one launch of `kernel` moves for one n-vertex graph."""
-    return {
+def alg_bytes_per_launch(kernel, n, launches=1.0, stats=None):
+    """Algorithmic HBM bytes one launch of `kernel` moves on average for one
+    n-vertex graph.  The tree kernels are launched a fixed number of times per
+    forward and return at once when the tree is already complete, so their
+    per-launch figure is the work of the launches that ran (stats: the tree's
+    own count of passes over W) spread over all launches."""
+    stats = stats or {}
+    per = {
         "fill_kernel": 8.0 * n * n,          # M (fp32) + idx (int32) written once
-        "tree_pass_kernel": 4.0 * n * n,     # W read once
         "prim_single_kernel": 4.0 * n * n,   # W read once (one row per Prim step)
-        # candidate lists (K u64 per vertex) + list pointers, labels, parents
-        "tree_rounds_kernel": (8.0 * K_LIST + 12.0) * n,
-    }.get(kernel)
+    }
+    if kernel in per:
+        return per[kernel]
+    if kernel == "tree_pass_kernel":         # W read once per pass that ran
+        return 4.0 * n * n * stats.get("passes", launches) / launches
+    if kernel == "tree_rounds_kernel":       # candidate lists (32 B per 4 entries) + labels
+        return (8.0 * K_LIST + 12.0) * n * stats.get("passes", launches) / launches
+    return None
 
 
 def source_sha(paths):
@@ -157,7 +166,8 @@ def bench_single(appd, torch, W, n, steps, warmup):
     t1.record()
     torch.cuda.synchronize()
     graph_ms = elapsed(t0, t1) / steps
-    return Wd, ms, census, dominant, launches / steps, avg_launch_ms, graph_ms
+    stats = appd.tree_stats(n, ws)
+    return Wd, ms, census, dominant, launches / steps, avg_launch_ms, graph_ms, stats
 
 
 def bench_batched(appd, torch, steps):
@@ -376,13 +386,13 @@ def main():
         wl = "single complete graph, n=%d points from the 10-component mixture (seed 2)" % n
     wl_key = "single-%d" % n
     print("step single-graph forward n=%d" % n, file=sys.stderr, flush=True)
-    Wd, ms, census, dom, dom_launches, dom_ms, graph_ms = bench_single(appd, torch, W, n,
-                                                                      args.steps, args.warmup)
+    Wd, ms, census, dom, dom_launches, dom_ms, graph_ms, stats = bench_single(
+        appd, torch, W, n, args.steps, args.warmup)
     del Wd
     torch.cuda.empty_cache()
 
     entries = float(n) * n
-    alg = alg_bytes_per_launch(dom, n)
+    alg = alg_bytes_per_launch(dom, n, dom_launches, stats)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": None, "traffic": measured_traffic(dom, wl_key),
                 "alg_bytes_per_launch": alg, "launches_per_step": dom_launches,
@@ -410,6 +420,7 @@ def main():
         "graph_replay_ms_per_step": graph_ms,
         "graph_replay_value": entries / (graph_ms / 1e3),
         "kernels": census,
+        "tree": stats,
         "roofline": roofline,
     }
     if not args.no_batches:

@@ -44,6 +44,7 @@ SIGNATURES = {
     "appd_tree": ([_P, _I, _I, _P, _P, _P, _SZ, _P], _I),
     "appd_fill": ([_I, _I, _P, _SZ, _P, _P, _P], _I),
     "appd_linkage": ([_P, _I, _I, _P, _P, _SZ, _P], _I),
+    "appd_tree_stats": ([_I, _I, _P, _SZ, _P, _P], _I),
     "appd_batch_workspace_bytes": ([_P, _I], _SZ),
     "appd_batch_prepare": ([_P, _I, _P, _SZ, _P, _P], _I),
     "appd_forward_batched": ([_P, _I, _P, _P, _P, _P, _P, _P], _I),
@@ -171,6 +172,16 @@ def forward(W: torch.Tensor, mode: int = MINIMAX, return_tree: bool = False, out
     if return_tree:
         return M, idx, order, parent
     return M, idx
+
+
+def tree_stats(n: int, workspace: torch.Tensor, mode: int = MINIMAX, tree: str = "auto") -> dict:
+    """What the last spanning-tree run in `workspace` did: Boruvka or Prim,
+    passes over W, Boruvka rounds, fallback to Prim."""
+    st = (ctypes.c_int32 * 4)()
+    _check(lib().appd_tree_stats(int(n), _mode(mode, tree), _ptr(workspace), workspace.numel(),
+                                 ctypes.cast(st, ctypes.c_void_p), _stream(workspace.device)),
+           "appd_tree_stats")
+    return {"boruvka": bool(st[0]), "passes": st[1], "rounds": st[2], "fallback": bool(st[3])}
 
 
 def linkage(W: torch.Tensor, mode: int = MINIMAX, tree: str = "auto",

@@ -110,6 +110,25 @@ int appd_fill(int n, int mode, const void* ws, size_t ws_bytes, float* M, int32_
     return ok();
 }
 
+int appd_tree_stats(int n, int mode, const void* ws, size_t ws_bytes, int32_t* stats,
+                    void* stream) {
+    if (bad_n(n) || !ws || !stats || !appd::valid_mode(mode)) return fail(APPD_EINVAL);
+    if (ws_bytes < appd::single_workspace_bytes(n) || ((uintptr_t)ws & 255u)) return fail(APPD_EINVAL);
+    const int algo = mode & 0x30;
+    const bool parallel =
+        algo == APPD_TREE_BORUVKA || (algo == APPD_TREE_AUTO && n >= appd::parallel_tree_min_n());
+    stats[0] = parallel ? 1 : 0;
+    stats[1] = stats[2] = stats[3] = 0;
+    if (!parallel || n < 2) return ok();
+    appd::SingleWs w = appd::carve_single(const_cast<void*>(ws), n);
+    if (appd::tree_stats(w.tree_ws, n, &stats[1], &stats[2], &stats[3], (hipStream_t)stream) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return fail(APPD_EHIP);
+    }
+    return ok();
+}
+
 int appd_linkage(const float* W, int n, int mode, double* Z, void* ws, size_t ws_bytes,
                  void* stream) {
     if (bad_n(n) || !W || (!Z && n > 1) || !ws || !appd::valid_mode(mode))

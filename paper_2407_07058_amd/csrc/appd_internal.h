@@ -43,9 +43,12 @@ size_t tree_workspace_bytes(int n);
 struct PrimOut;
 hipError_t run_tree_parallel(const float* W, int n, int mode, const PrimOut& out, void* tws,
                              hipStream_t s);
+hipError_t tree_stats(const void* tws, int n, int32_t* passes, int32_t* rounds, int32_t* fallback,
+                      hipStream_t s);
 hipError_t run_linkage(const float* W, int n, int mode, const PrimOut& out, void* tws, double* Z,
                        hipStream_t s);
 bool valid_mode(int mode);
+int parallel_tree_min_n();
 
 size_t single_workspace_bytes(int n);
 SingleWs carve_single(void* ws, int n);

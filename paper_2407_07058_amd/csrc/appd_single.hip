@@ -138,6 +138,7 @@ SingleWs carve_single(void* ws, int n) {
 
 // below this size Prim's sequential chain is short enough
 constexpr int kParallelTreeMinN = 512;
+int parallel_tree_min_n() { return kParallelTreeMinN; }
 
 bool valid_mode(int mode) {
     if (mode & ~0x31) return false;

@@ -55,7 +55,7 @@ constexpr int kGroupWords = 8;
 #endif
 
 // control block (int32 words); word 32 holds the number of rank tiles
-enum { C_DONE = 0, C_NCOMP, C_NEED_PASS, C_FALLBACK, C_ROUNDS, C_ORDERED, C_WORDS };
+enum { C_DONE = 0, C_NCOMP, C_NEED_PASS, C_FALLBACK, C_ROUNDS, C_ORDERED, C_PASSES, C_WORDS };
 constexpr int C_TILES = 32;
 
 // List entries are ord32(w) << 32 | v: within one row the flat index of (u, v)
@@ -107,8 +107,9 @@ __global__ __launch_bounds__(kPassThreads) void tree_pass_kernel(const float* __
                                                                  const int32_t* __restrict__ comp,
                                                                  int32_t* __restrict__ lptr,
                                                                  uint32_t* __restrict__ groups,
-                                                                 const int32_t* __restrict__ ctrl) {
+                                                                 int32_t* __restrict__ ctrl) {
     if (ctrl[C_DONE]) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctrl[C_PASSES], 1);  // passes that ran
     const int lane = threadIdx.x & (kWave - 1);
     const int u = blockIdx.x * (kPassThreads / kWave) + threadIdx.x / kWave;
     if (u >= n) return;  // no barrier in this kernel
@@ -1402,4 +1403,21 @@ hipError_t run_linkage(const float* W, int n, int mode, const PrimOut& out, void
     return hipSuccess;
 }
 
+}  // namespace appd
+
+namespace appd {
+// Passes over W and Boruvka rounds the last parallel-tree run used, and
+// whether it fell back to sequential Prim (read from the control words).
+hipError_t tree_stats(const void* tws, int n, int32_t* passes, int32_t* rounds, int32_t* fallback,
+                      hipStream_t s) {
+    TreeWs w = carve_tree(const_cast<void*>(tws), n);
+    int32_t c[C_WORDS];
+    hipError_t e = hipMemcpyAsync(c, w.ctrl, sizeof(c), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    *passes = c[C_PASSES];
+    *rounds = c[C_ROUNDS];
+    *fallback = c[C_FALLBACK];
+    return hipSuccess;
+}
 }  // namespace appd

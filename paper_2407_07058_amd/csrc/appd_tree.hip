@@ -55,7 +55,13 @@ constexpr int kGroupWords = 8;
 #endif
 
 // control block (int32 words); word 32 holds the number of rank tiles
-enum { C_DONE = 0, C_NCOMP, C_NEED_PASS, C_FALLBACK, C_ROUNDS, C_ORDERED, C_PASSES, C_WORDS };
+enum { C_DONE = 0, C_NCOMP, C_NEED_PASS, C_FALLBACK, C_ROUNDS, C_ORDERED, C_PASSES, C_CMAT,
+       C_WORDS };
+// With at most kCmat components left, a refresh pass computes the smallest
+// edge key between every pair of components instead of candidate lists
+// (C_CMAT = the number of components it saw); the next rounds call then
+// finishes the tree from that exact kCmat x kCmat table.
+constexpr int kCmat = 16;
 constexpr int C_TILES = 32;
 
 // List entries are ord32(w) << 32 | v: within one row the flat index of (u, v)
@@ -108,7 +114,7 @@ __global__ __launch_bounds__(kPassThreads) void tree_pass_kernel(const float* __
                                                                  int32_t* __restrict__ lptr,
                                                                  uint32_t* __restrict__ groups,
                                                                  int32_t* __restrict__ ctrl) {
-    if (ctrl[C_DONE]) return;
+    if (ctrl[C_DONE] || (FILTER && ctrl[C_NCOMP] <= kCmat)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctrl[C_PASSES], 1);  // passes that ran
     const int lane = threadIdx.x & (kWave - 1);
     const int u = blockIdx.x * (kPassThreads / kWave) + threadIdx.x / kWave;
@@ -212,6 +218,104 @@ __global__ __launch_bounds__(kPassThreads) void tree_pass_kernel(const float* __
     if (lane == 0) lptr[u] = 0;
 }
 
+// ---------------------------------------------------------------- component table
+// Refresh pass for at most kCmat components (dense ids 0..C-1), computing the
+// smallest edge key between every pair of components.  By the cut property the
+// spanning tree of the components under these minima is exactly the rest of
+// the minimum spanning tree.
+//
+// A persistent grid of kCmatBlocks(n) workgroups of 16 waves, one row per wave
+// at a time.  Each lane keeps, per component c, the smallest weight it has
+// seen towards c and its column in a private LDS column ({s, v}; s = w, or -w
+// when widest).  W is NaN-free, so a float compare orders weights exactly like
+// ord32 (both take -0.0 = +0.0); the empty slot holds a NaN, which every
+// weight beats, and a lane walks its columns in increasing order, so the first
+// of equal weights (the smaller edge key within the row) is kept.  At the end
+// of a row lane l reduces slot l & 15 over a quarter of the wave's lanes as
+// full edge keys and two shuffles finish the row; the 16 row minima fold into
+// the workgroup's table with LDS atomics.  Each workgroup writes its table to
+// part[blockIdx]; the next rounds call combines the tables (the kernel
+// boundary publishes them, so no workgroup waits on or fences for another).
+constexpr int kCmatThreads = 1024;
+constexpr int kCmatMaxBlocks = 256;
+__host__ __device__ inline int kCmatBlocks(int n) {
+    const int b = (n + kCmatThreads / kWave - 1) / (kCmatThreads / kWave);
+    return b < kCmatMaxBlocks ? b : kCmatMaxBlocks;
+}
+
+__device__ __forceinline__ void cmat_fold_slot(uint2* slot, float s, uint32_t v) {
+    const uint2 cur = *slot;
+    if (!(s >= __uint_as_float(cur.x))) *slot = make_uint2(__float_as_uint(s), v);
+}
+
+template <bool WIDEST, bool VEC>
+__global__ __launch_bounds__(kCmatThreads) void tree_cmat_kernel(const float* __restrict__ W,
+                                                                 int n,
+                                                                 const int32_t* __restrict__ comp,
+                                                                 uint64_t* __restrict__ part,
+                                                                 int32_t* __restrict__ ctrl) {
+    constexpr int NW = kCmatThreads / kWave;
+    __shared__ uint2 tab[NW][kCmat][kWave];
+    __shared__ uint64_t pair[kCmat * kCmat];
+    if (ctrl[C_DONE]) return;
+    const int C = ctrl[C_NCOMP];
+    if (C > kCmat) return;
+    const int t = threadIdx.x, lane = t & (kWave - 1), wid = t / kWave;
+    if (blockIdx.x == 0 && t == 0) {
+        atomicAdd(&ctrl[C_PASSES], 1);
+        ctrl[C_CMAT] = C;
+    }
+    if (t < kCmat * kCmat) pair[t] = kNone;
+    uint2* col = &tab[wid][0][lane];  // slot c at col[c * kWave]
+    const uint2 empty = make_uint2(0x7fc00000u, 0xffffffffu);
+#pragma unroll
+    for (int c = 0; c < kCmat; ++c) col[c * kWave] = empty;
+    __syncthreads();
+    const int nw = gridDim.x * NW;
+    for (int u = blockIdx.x * NW + wid; u < n; u += nw) {
+        const float* row = W + (size_t)u * (size_t)n;
+        const int cu = comp[u] & (kCmat - 1);
+        if (VEC) {
+            float4 x = *(const float4*)(row + (lane * 4 < n ? lane * 4 : 0));
+            int4 c4 = *(const int4*)(comp + (lane * 4 < n ? lane * 4 : 0));
+            for (int c0 = lane * 4; c0 < n; c0 += kWave * 4) {
+                const int c1 = c0 + kWave * 4 < n ? c0 + kWave * 4 : c0;  // prefetch
+                const float4 xn = *(const float4*)(row + c1);
+                const int4 cn = *(const int4*)(comp + c1);
+                cmat_fold_slot(&col[(c4.x & (kCmat - 1)) * kWave], WIDEST ? -x.x : x.x, c0);
+                cmat_fold_slot(&col[(c4.y & (kCmat - 1)) * kWave], WIDEST ? -x.y : x.y, c0 + 1);
+                cmat_fold_slot(&col[(c4.z & (kCmat - 1)) * kWave], WIDEST ? -x.z : x.z, c0 + 2);
+                cmat_fold_slot(&col[(c4.w & (kCmat - 1)) * kWave], WIDEST ? -x.w : x.w, c0 + 3);
+                x = xn;
+                c4 = cn;
+            }
+        } else {
+            for (int c = lane; c < n; c += kWave) {
+                const float x = row[c];
+                cmat_fold_slot(&col[(comp[c] & (kCmat - 1)) * kWave], WIDEST ? -x : x, c);
+            }
+        }
+        // slot (lane & 15) over lanes 16 q .. 16 q + 15, then across the quarters
+        const int c = lane & (kCmat - 1), q = lane / kCmat;
+        uint64_t m = kNone;
+#pragma unroll
+        for (int j = 0; j < kWave / 4; ++j) {
+            const uint2 e = tab[wid][c][q * (kWave / 4) + j];
+            const uint64_t key = ((uint64_t)ord32(__uint_as_float(e.x)) << 32) |
+                                 (uint64_t)flat_idx((uint32_t)u, e.y, (uint32_t)n);
+            m = umin64(m, e.y == 0xffffffffu ? kNone : key);
+        }
+        m = umin64(m, shfl_xor_u64(m, 16));
+        m = umin64(m, shfl_xor_u64(m, 32));
+#pragma unroll
+        for (int c2 = 0; c2 < kCmat; ++c2) col[c2 * kWave] = empty;
+        if (lane < kCmat && m != kNone)
+            atomicMin((unsigned long long*)&pair[cu * kCmat + c], (unsigned long long)m);
+    }
+    __syncthreads();
+    if (t < kCmat * kCmat) part[(size_t)blockIdx.x * kCmat * kCmat + t] = pair[t];
+}
+
 // ---------------------------------------------------------------- rounds
 struct RoundArgs {
     const float* W;
@@ -226,6 +330,7 @@ struct RoundArgs {
     int32_t* hy;  // endpoint outside
     int32_t* par;
     int32_t* ctrl;
+    const uint64_t* cmpart;  // component-table pass: kCmatBlocks(n) tables of kCmat^2 keys
     int cm;  // capacity of the per-component LDS tables
 };
 
@@ -332,6 +437,35 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
     };
     // the rooted forest built so far (first call: every vertex its own root)
     const bool first = ctrl[C_ROUNDS] == 0;
+    // after a component-table pass: c0 components, table entry (a, b) names the
+    // smallest edge between them; s_cmap follows each one's current number
+    __shared__ int s_cmap[kCmat];
+    __shared__ uint64_t s_cm[kCmat * kCmat];
+    const int c0 = first ? 0 : ctrl[C_CMAT];
+    const bool dmode = c0 > 0 && c0 == C;
+    if (t < kCmat) s_cmap[t] = t;
+    if (dmode) {
+        // combine the component-table pass's workgroup tables: thread t takes
+        // entry t % 256 of every fourth table, eight loads in flight at a time
+        static_assert(kRoundThreads == 4 * kCmat * kCmat, "four threads per table entry");
+        const int e = t % (kCmat * kCmat), q = t / (kCmat * kCmat);
+        const int nparts = kCmatBlocks(n);
+        if (t < kCmat * kCmat) s_cm[t] = kNone;
+        uint64_t m = kNone;
+        for (int g0 = q; g0 < nparts; g0 += 4 * 8) {
+            uint64_t v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int g = g0 + 4 * i;
+                v[i] = a.cmpart[(size_t)(g < nparts ? g : q) * kCmat * kCmat + e];
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) m = umin64(m, v[i]);
+        }
+        __syncthreads();
+        atomicMin((unsigned long long*)&s_cm[e], (unsigned long long)m);
+        __syncthreads();
+    }
     if (LDS && first && !ctrl[C_DONE]) {
         // Round 1, all in LDS.  Every vertex is its own component and its list's
         // first entry is its cheapest edge, so it hooks along it; the only
@@ -452,7 +586,16 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
             s_flag[0] = 0;  // components that decided this round
             ctrl[C_ROUNDS] += 1;
         }
-        for (int base = 0; base < n; base += kStride) {
+        if (dmode) {
+            // exact: every component's cheapest edge to any other one
+            for (int e = t; e < c0 * c0; e += kRoundThreads) {
+                const int x = e / c0, y = e % c0;
+                const int cx = s_cmap[x], cy = s_cmap[y];
+                const uint64_t k = s_cm[x * kCmat + y];
+                if (cx != cy && k != kNone) min_best(cx, k);
+            }
+        }
+        for (int base = 0; !dmode && base < n; base += kStride) {
             int pp[kW];
             uint4 gr[kW];  // ids (x, y) and ords of entries 0, 1 (z, w) of the group
             uint2 go[kW];  // ords of entries 2, 3
@@ -658,7 +801,9 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
         const int Cn = s_flag[2];
         // 6. relabel every vertex; clear the tables for the next round
         for (int u = t; u < n; u += kRoundThreads) setc(u, gethx(geth(getc(u))));
+        const int cmap_new = (dmode && t < c0) ? gethx(geth(s_cmap[t])) : 0;
         __syncthreads();
+        if (dmode && t < c0) s_cmap[t] = cmap_new;
         C = Cn;
         small = C <= cm;
         for (int d = t; d < C; d += kRoundThreads) {
@@ -674,6 +819,7 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
     }
     __syncthreads();
     const bool done = ctrl[C_DONE] != 0;
+    if (dmode && t == 0) ctrl[C_CMAT] = 0;  // the table is used up
     if (done && t == 0) {  // re-root at vertex 0
         int cur = 0, prev = -1;
         while (cur >= 0) {
@@ -1104,6 +1250,7 @@ struct TreeWs {
     int32_t *comp, *lptr, *hook, *hx, *hy, *par, *link, *size, *gcount, *gstart, *gfill;
     int32_t *tstart, *grouped, *rank, *sorted_size, *sorted_grp, *sorted_pre;
     uint64_t *best, *lb, *keyup;
+    uint64_t* cmpart;
     int32_t* ctrl;
     size_t bytes;
 };
@@ -1126,6 +1273,7 @@ static TreeWs carve_tree(void* ws, int n) {
     uint64_t** longs[3] = {&w.best, &w.lb, &w.keyup};
     for (int i = 0; i < 3; ++i) *longs[i] = (uint64_t*)take(8 * (size_t)n);
     w.ctrl = (int32_t*)take(4 * 64);
+    w.cmpart = (uint64_t*)take(8 * (size_t)kCmat * kCmat * kCmatBlocks(n));
     w.bytes = off;
     int32_t* r = (int32_t*)w.lists;
     w.tstart = r;
@@ -1176,6 +1324,20 @@ static void launch_pass(const float* W, int n, const TreeWs& w, hipStream_t s) {
 }
 
 template <bool WIDEST>
+static void launch_cmat(const float* W, int n, const TreeWs& w, hipStream_t s) {
+    const int blocks = kCmatBlocks(n);
+    const bool vec = (n % 4 == 0) && (((uintptr_t)W & 15u) == 0);
+    if (vec)
+        APPD_LAUNCH("tree_cmat_kernel", s,
+            tree_cmat_kernel<WIDEST, true><<<blocks, kCmatThreads, 0, s>>>(W, n, w.comp,
+                w.cmpart, w.ctrl));
+    else
+        APPD_LAUNCH("tree_cmat_kernel", s,
+            tree_cmat_kernel<WIDEST, false><<<blocks, kCmatThreads, 0, s>>>(W, n, w.comp,
+                w.cmpart, w.ctrl));
+}
+
+template <bool WIDEST>
 static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* tws,
                                       hipStream_t s) {
     TreeWs w = carve_tree(tws, n);
@@ -1198,10 +1360,15 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
         if (e != hipSuccess) return e;
     }
     RoundArgs ra{W,      n,    w.comp, w.best, w.lb, w.lptr, (const uint32_t*)w.lists,
-                 w.hook, w.hx, w.hy,   w.par,  w.ctrl, cm};
+                 w.hook, w.hx, w.hy,   w.par,  w.ctrl, w.cmpart, cm};
     for (int p = 0; p < kPasses; ++p) {
-        if (p == 0) launch_pass<WIDEST, false>(W, n, w, s);
-        else launch_pass<WIDEST, true>(W, n, w, s);
+        if (p == 0) {
+            launch_pass<WIDEST, false>(W, n, w, s);
+        } else {  // candidate lists, or the component table once few are left
+            launch_pass<WIDEST, true>(W, n, w, s);
+            APPD_CHK();
+            launch_cmat<WIDEST>(W, n, w, s);
+        }
         APPD_CHK();
         if (lds)
             APPD_LAUNCH("tree_rounds_kernel", s,

@@ -111,3 +111,26 @@ def test_boruvka_uniform_full_sampled():
     Mo, io = oracle.appd_rows(W, rows)
     assert np.array_equal(Ma[rows].cpu().numpy().view(np.uint32), Mo.view(np.uint32))
     assert np.array_equal(Ia[rows].cpu().numpy(), io)
+
+
+@pytest.mark.parametrize("k,mode", [(3, appd.MINIMAX), (12, appd.MINIMAX), (12, appd.WIDEST)])
+def test_boruvka_component_table(k, mode):
+    """A few far-apart clusters: the candidate lists stay inside the clusters, so
+    after the first rounds at most 16 components remain and the refresh pass
+    builds the table of smallest inter-component edges, from which the tree is
+    finished exactly.  Bit-exact against the oracle; no fallback to Prim."""
+    say("case boruvka component table k=%d mode=%d" % (k, mode))
+    rng = np.random.default_rng(40 + k)
+    centres = rng.random((k, 4)) * 100
+    X = centres[rng.integers(0, k, 2400)] + 0.3 * rng.standard_normal((2400, 4))
+    W = workloads.euclid_w(X)
+    Wd = torch.from_numpy(W).to(DEV)
+    ws = torch.empty(appd.workspace_bytes(2400), dtype=torch.uint8, device=DEV)
+    M, idx = appd.forward(Wd, mode=mode, tree="boruvka", workspace=ws)
+    torch.cuda.synchronize()
+    st = appd.tree_stats(2400, ws, mode=mode, tree="boruvka")
+    ref = oracle.appd_widest if mode == appd.WIDEST else oracle.appd
+    Mo, io = ref(W)
+    assert np.array_equal(M.cpu().numpy().view(np.uint32), Mo.view(np.uint32))
+    assert np.array_equal(idx.cpu().numpy(), io)
+    assert st["boruvka"] and not st["fallback"] and st["passes"] >= 1, st

@@ -287,9 +287,10 @@ __device__ __forceinline__ void fill_rows_block(const int32_t* __restrict__ pos,
 // The same fill on 32-bit slot codes (fill_prep_block): the running maxima
 // are taken over codes, which order like the keys, and each output is decoded
 // through the block's tables in LDS.  The two boundary keys of a row (not gap
-// values) are coded between the gaps by a binary search in the sorted gaps,
-// with per-wave decode entries at CB + 2 * wave (left) and CB + 2 * wave + 1
-// (right).  s_R: this wave's row buffer of CB codes; s_dM / s_dI: CB + 2 *
+// values) are coded between the gaps by their rank among the sorted gaps
+// (a two-step ballot search), with per-wave decode entries at CB + 2 * wave
+// (left) and CB + 2 * wave + 1 (right).  A wave locates its next row and
+// issues that row's ek loads before it fills the current one.  s_R: this wave's row buffer of CB codes; s_dM / s_dI: CB + 2 *
 // nwaves entries.
 template <int CB, bool WIDEST, bool VEC>
 __device__ __forceinline__ void fill_rows_block_coded(
@@ -300,7 +301,8 @@ __device__ __forceinline__ void fill_rows_block_coded(
     constexpr int S = CB / kWave;
     static_assert(S >= 1 && S <= kWave, "CB must be in [64, 4096]");
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
+    // wave-uniform, so the per-row position loads are scalar loads
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int k0 = lane * S;
     uint32_t g[S];  // codes of slots k0 + q; padding slots hold 0
 #pragma unroll
@@ -309,45 +311,73 @@ __device__ __forceinline__ void fill_rows_block_coded(
     if (lane == kWave - 1) gnx = 0;
     const int sp_last = s_sp[k0 + S - 1];  // padded slots hold 0xffff
     const uint32_t cl = (uint32_t)(CB + 2 * wid), cr = cl + 1;
-    auto code_of = [&](uint64_t key, uint32_t slot) -> uint32_t {
-        int lo = 0, hi = cnt - 1;  // gaps below key among s_sorted[0 .. cnt-2]
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_sorted[mid] < key) lo = mid + 1;
-            else hi = mid;
-        }
-        return ((uint32_t)(2 * lo + 1) << kCodeShift) | slot;
+    // Where a row's position a sits among the block's slots, and this lane's
+    // ek values of the positions between the two slots around it.
+    struct RowAt {
+        int a, ks, lo, hi, diag;
+        uint64_t e0, e1;
     };
-
-    int i = r0 + wid;
-    int a_next = i < r1 ? pos[i] : 0;
-    for (; i < r1; i += nwaves) {
-        const int a = a_next;
-        if (i + nwaves < r1) a_next = pos[i + nwaves];
-        // k* = number of slots whose position is below a
+    // Every load and store of a row is issued unconditionally (indices
+    // clamped), so the number of memory operations between a prefetch and its
+    // use is fixed and the wait for it leaves the stores of the row before in
+    // flight; loads for the next row are issued before the current one is
+    // filled.
+    auto locate = [&](int a) {
+        RowAt r;
+        r.a = a;
+        // ks = number of slots whose position is below a
         const int nbl = __popcll(__ballot(sp_last < a));
         const int base = nbl * S;
         const bool part = (lane < S) && (base + lane < CB) && (s_sp[min(base + lane, CB - 1)] < a);
-        const int ks = base + __popcll(__ballot(part));
-        const bool diag = ks < cnt && (int)s_sp[ks] == a;
+        r.ks = base + __popcll(__ballot(part));
+        r.diag = r.ks < cnt && (int)s_sp[r.ks] == a;
+        r.lo = r.ks > 0 ? (int)s_sp[r.ks - 1] + 1 : a + 1;
+        r.hi = r.ks < cnt ? (int)s_sp[r.ks] : a;  // a valid position even when lo > hi
+        r.e0 = ek[min(r.lo + lane, r.hi)];
+        r.e1 = ek[min(r.lo + kWave + lane, r.hi)];
+        return r;
+    };
+    // Rank of a boundary key among the sorted gaps in two steps: lane l probes
+    // gap S l + S - 1 (the last one of its S-run; entries from cnt - 1 on hold
+    // ~0, above every key), so the keys below a probe count whole runs; then
+    // one run of S entries is compared for each key at once (lanes 0..S-1 for
+    // the left key, 32..32+S-1 for the right one).
+    static_assert(S <= 32, "one run per half-wave");
+    const uint64_t probe = s_sorted[k0 + S - 1];
+    constexpr uint64_t kRunMask = S == 32 ? 0xffffffffull : ((1ull << S) - 1);
 
+    auto fill_row = [&](const RowAt& cur, int i) {
+        const int a = cur.a, ks = cur.ks;
         // codes of the keys crossed next to the row's own position
         uint32_t bl = 0, br = 0;
-        if (diag) {
+        if (cur.diag) {
             bl = ks > 0 ? s_code[ks] : 0u;
         } else {
-            const int lo = ks > 0 ? (int)s_sp[ks - 1] + 1 : a + 1;
-            const int hi = ks < cnt ? (int)s_sp[ks] : a;
             uint64_t kl = 0, kr = 0;
-            for (int x = lo + lane; x <= hi; x += kWave) {
+            {
+                const int x0 = cur.lo + lane, x1 = x0 + kWave;
+                const uint64_t e0 = x0 <= cur.hi ? cur.e0 : 0ull;
+                const uint64_t e1 = x1 <= cur.hi ? cur.e1 : 0ull;
+                kl = umax64(x0 <= a ? e0 : 0ull, x1 <= a ? e1 : 0ull);
+                kr = umax64(x0 > a ? e0 : 0ull, x1 > a ? e1 : 0ull);
+            }
+            for (int x = cur.lo + 2 * kWave + lane; x <= cur.hi; x += kWave) {  // long gaps
                 const uint64_t e = ek[x];
                 if (x <= a) kl = umax64(kl, e);
                 else kr = umax64(kr, e);
             }
             kl = wave_max_u64(kl);
             kr = wave_max_u64(kr);
-            if (kl) bl = code_of(kl, cl);
-            if (kr) br = code_of(kr, cr);
+            const int bL = min(__popcll(__ballot(probe < kl)), CB / S - 1);
+            const int bR = min(__popcll(__ballot(probe < kr)), CB / S - 1);
+            const int j = lane & 31;
+            const bool rgt = lane >= 32;
+            const uint64_t sv = s_sorted[(rgt ? bR : bL) * S + (j < S ? j : 0)];
+            const uint64_t m = __ballot(j < S && sv < (rgt ? kr : kl));
+            const int loL = bL * S + __popcll(m & kRunMask);
+            const int loR = bR * S + __popcll((m >> 32) & kRunMask);
+            if (kl) bl = ((uint32_t)(2 * loL + 1) << kCodeShift) | cl;
+            if (kr) br = ((uint32_t)(2 * loR + 1) << kCodeShift) | cr;
             if (lane == 0) {
                 s_dM[cl] = kl ? key_weight<WIDEST>(kl) : 0.0f;
                 s_dI[cl] = kl ? (int32_t)(uint32_t)kl : -1;
@@ -389,7 +419,11 @@ __device__ __forceinline__ void fill_rows_block_coded(
         float* mrow = M + (size_t)i * (size_t)n + j0;
         int32_t* irow = idx + (size_t)i * (size_t)n + j0;
         if (VEC) {
-            for (int c = lane * 4; c < cnt; c += kWave * 4) {
+            // cnt is a multiple of 4; a short block repeats its last four
+            // columns (the same values to the same addresses)
+#pragma unroll
+            for (int it = 0; it < CB / (4 * kWave); ++it) {
+                const int c = min(lane * 4 + it * 4 * kWave, cnt - 4);
                 const uint64_t sl = *(const uint64_t*)(s_slot + c);  // 4 slots
                 const uint32_t c0 = s_R[sl & 0xffff] & kCodeMask;
                 const uint32_t c1 = s_R[(sl >> 16) & 0xffff] & kCodeMask;
@@ -406,6 +440,32 @@ __device__ __forceinline__ void fill_rows_block_coded(
             }
         }
         wave_lds_sync();
+    };
+
+    // rows r0 + wid, + nwaves, ...: two row states in turn (no register holding
+    // a load in flight is copied).  The first row is peeled so that every
+    // path into the loop has issued the same loads and stores.
+    int i = r0 + wid;
+    if (i >= r1) return;
+    const int last = r1 - 1;
+    RowAt A = locate(pos[i]), B;
+    int pa = pos[min(i + nwaves, last)], pb;
+    pb = pos[min(i + 2 * nwaves, last)];
+    B = locate(pa);
+    asm volatile("" ::: "memory");  // issue the next row's loads before these stores
+    fill_row(A, i);
+    for (i += nwaves; i < r1;) {
+        pa = pos[min(i + 2 * nwaves, last)];
+        A = locate(pb);
+        asm volatile("" ::: "memory");
+        fill_row(B, i);
+        i += nwaves;
+        if (i >= r1) break;
+        pb = pos[min(i + 2 * nwaves, last)];
+        B = locate(pa);
+        asm volatile("" ::: "memory");
+        fill_row(A, i);
+        i += nwaves;
     }
 }
 

@@ -295,8 +295,9 @@ __device__ __forceinline__ void fill_rows_block(const int32_t* __restrict__ pos,
 template <int CB, bool WIDEST, bool VEC>
 __device__ __forceinline__ void fill_rows_block_coded(
     const int32_t* __restrict__ pos, const uint64_t* __restrict__ ek, int n, int j0, int cnt,
-    int r0, int r1, const uint16_t* s_sp, const uint16_t* s_slot, const uint32_t* s_code,
-    const uint64_t* s_sorted, float* s_dM, int32_t* s_dI, uint32_t* s_R, float* __restrict__ M,
+    int r0, int r1, const uint16_t* s_sp, const uint16_t* s_slot,
+    const uint32_t* __restrict__ code, const uint64_t* s_sorted, float* s_dM, int32_t* s_dI,
+    uint32_t* s_R, float* __restrict__ M,
     int32_t* __restrict__ idx, int nwaves) {
     constexpr int S = CB / kWave;
     static_assert(S >= 1 && S <= kWave, "CB must be in [64, 4096]");
@@ -304,9 +305,9 @@ __device__ __forceinline__ void fill_rows_block_coded(
     // wave-uniform, so the per-row position loads are scalar loads
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int k0 = lane * S;
-    uint32_t g[S];  // codes of slots k0 + q; padding slots hold 0
+    uint32_t g[S];  // codes of slots k0 + q (the block's code[0 .. cnt)); padding slots hold 0
 #pragma unroll
-    for (int q = 0; q < S; ++q) g[q] = s_code[k0 + q];
+    for (int q = 0; q < S; ++q) g[q] = k0 + q < cnt ? code[k0 + q] : 0u;
     uint32_t gnx = __shfl_down(g[0], 1);  // code of slot k0 + S
     if (lane == kWave - 1) gnx = 0;
     const int sp_last = s_sp[k0 + S - 1];  // padded slots hold 0xffff
@@ -351,7 +352,11 @@ __device__ __forceinline__ void fill_rows_block_coded(
         // codes of the keys crossed next to the row's own position
         uint32_t bl = 0, br = 0;
         if (cur.diag) {
-            bl = ks > 0 ? s_code[ks] : 0u;
+            // the code of slot ks: entry ks % S of lane ks / S (uniform index)
+            uint32_t gk = 0;
+#pragma unroll
+            for (int q = 0; q < S; ++q) gk = q == ks % S ? g[q] : gk;
+            bl = ks > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)gk, ks / S) : 0u;
         } else {
             uint64_t kl = 0, kr = 0;
             {

@@ -42,7 +42,6 @@ __global__ __launch_bounds__(kFillThreads) void fill_kernel(const int32_t* __res
     constexpr int NWV = kFillThreads / kWave;
     __shared__ uint16_t s_sp[CB];
     __shared__ __align__(16) uint16_t s_slot[CB];
-    __shared__ uint32_t s_code[CB];
     __shared__ uint64_t s_sorted[CB];
     __shared__ float s_dM[CB + 2 * NWV];
     __shared__ int32_t s_dI[CB + 2 * NWV];
@@ -53,7 +52,6 @@ __global__ __launch_bounds__(kFillThreads) void fill_kernel(const int32_t* __res
         const bool in = k < cnt;
         s_sp[k] = in ? w.blk_sp[j0 + k] : (uint16_t)0xffff;
         s_slot[k] = in ? w.blk_slot[j0 + k] : (uint16_t)0;
-        s_code[k] = in ? w.blk_code[j0 + k] : 0u;
         s_sorted[k] = in ? w.blk_sorted[j0 + k] : ~0ull;
         s_dM[k] = in ? w.blk_dM[j0 + k] : 0.0f;
         s_dI[k] = in ? w.blk_dI[j0 + k] : -1;
@@ -61,9 +59,9 @@ __global__ __launch_bounds__(kFillThreads) void fill_kernel(const int32_t* __res
     __syncthreads();
     const int r0 = blockIdx.y * rows_per_wg;
     const int r1 = min(n, r0 + rows_per_wg);
-    fill_rows_block_coded<CB, WIDEST, VEC>(pos, ek, n, j0, cnt, r0, r1, s_sp, s_slot, s_code,
-                                           s_sorted, s_dM, s_dI, s_R[threadIdx.x / kWave], M, idx,
-                                           NWV);
+    fill_rows_block_coded<CB, WIDEST, VEC>(pos, ek, n, j0, cnt, r0, r1, s_sp, s_slot,
+                                           w.blk_code + j0, s_sorted, s_dM, s_dI,
+                                           s_R[threadIdx.x / kWave], M, idx, NWV);
 }
 
 // ---------------------------------------------------------------- launchers

@@ -305,11 +305,30 @@ __device__ __forceinline__ void fill_rows_block_coded(
     // wave-uniform, so the per-row position loads are scalar loads
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int k0 = lane * S;
-    uint32_t g[S];  // codes of slots k0 + q (the block's code[0 .. cnt)); padding slots hold 0
+    static_assert(S == 16, "the slots of one lane spread over one 16-lane DPP row");
+    // Row-independent running maxima of this lane's slot codes (the block's
+    // code[0 .. cnt), padding slots 0): pre[q] = max code[k0 .. k0+q] (going up
+    // from below the lane), suf[q] = max code[k0+q+1 .. k0+S] (going down from
+    // above it).
+    uint32_t pre[S], suf[S];
+    {
+        uint32_t g[S];
 #pragma unroll
-    for (int q = 0; q < S; ++q) g[q] = k0 + q < cnt ? code[k0 + q] : 0u;
-    uint32_t gnx = __shfl_down(g[0], 1);  // code of slot k0 + S
-    if (lane == kWave - 1) gnx = 0;
+        for (int q = 0; q < S; ++q) g[q] = k0 + q < cnt ? code[k0 + q] : 0u;
+        uint32_t run = __shfl_down(g[0], 1);  // code of slot k0 + S
+        if (lane == kWave - 1) run = 0;
+#pragma unroll
+        for (int q = S - 1; q >= 0; --q) {
+            suf[q] = run;
+            run = max(run, g[q]);
+        }
+        run = 0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            run = max(run, g[q]);
+            pre[q] = run;
+        }
+    }
     const int sp_last = s_sp[k0 + S - 1];  // padded slots hold 0xffff
     const uint32_t cl = (uint32_t)(CB + 2 * wid), cr = cl + 1;
     // Where a row's position a sits among the block's slots, and this lane's
@@ -317,6 +336,12 @@ __device__ __forceinline__ void fill_rows_block_coded(
     struct RowAt {
         int a, ks, lo, hi, diag;
         uint64_t e0, e1;
+        uint32_t c;  // lanes 0..15: code of slot S su + j; 16..31: of slot S sd + j + 1
+    };
+    // su = lane holding slot ks (kWave: none), sd = lane holding slot ks - 1 (-1: none)
+    auto lanes_around = [&](int ks, int& su, int& sd) {
+        su = ks / S;
+        sd = (ks + S - 1) / S - 1;
     };
     // Every load and store of a row is issued unconditionally (indices
     // clamped), so the number of memory operations between a prefetch and its
@@ -336,6 +361,11 @@ __device__ __forceinline__ void fill_rows_block_coded(
         r.hi = r.ks < cnt ? (int)s_sp[r.ks] : a;  // a valid position even when lo > hi
         r.e0 = ek[min(r.lo + lane, r.hi)];
         r.e1 = ek[min(r.lo + kWave + lane, r.hi)];
+        int su, sd;
+        lanes_around(r.ks, su, sd);
+        const int j = lane & 15;
+        const int ci = lane < 16 ? su * S + j : (lane < 32 ? sd * S + j + 1 : 0);
+        r.c = code[min(max(ci, 0), cnt - 1)];  // used only where ci < cnt
         return r;
     };
     // Rank of a boundary key among the sorted gaps in two steps: lane l probes
@@ -352,11 +382,8 @@ __device__ __forceinline__ void fill_rows_block_coded(
         // codes of the keys crossed next to the row's own position
         uint32_t bl = 0, br = 0;
         if (cur.diag) {
-            // the code of slot ks: entry ks % S of lane ks / S (uniform index)
-            uint32_t gk = 0;
-#pragma unroll
-            for (int q = 0; q < S; ++q) gk = q == ks % S ? g[q] : gk;
-            bl = ks > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)gk, ks / S) : 0u;
+            // the code of slot ks (< cnt), held by lane ks % S
+            bl = ks > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)cur.c, ks % S) : 0u;
         } else {
             uint64_t kl = 0, kr = 0;
             {
@@ -391,34 +418,46 @@ __device__ __forceinline__ void fill_rows_block_coded(
             }
         }
 
-        // lane-local running maxima: upward over slots >= k*, downward below
-        uint32_t loc[S];
-        uint32_t run = 0;
-#pragma unroll
-        for (int q = 0; q < S; ++q) {
-            const int k = k0 + q;
-            const uint32_t e = k > ks ? g[q] : (k == ks ? br : 0u);
-            run = max(run, e);
-            loc[q] = run;
+        // R[k] = max code crossed from the row's position to slot k: upward
+        // (k >= ks) br then code[ks+1 .. k], downward (k < ks) bl then
+        // code[k+1 .. ks-1].  Lanes wholly above su or below sd take their
+        // slots from pre / suf and the maxima of the lanes between them and
+        // ks; the slots of su and sd go one per lane to lanes 0..15 and 16..31
+        // and are scanned there (inclusive, up resp. down the 16-lane row).
+        int su, sd;
+        lanes_around(ks, su, sd);
+        const int j = lane & 15;
+        uint32_t e = 0;
+        if (lane < 16) {
+            const int k = su * S + j;
+            e = k > ks ? (k < cnt ? cur.c : 0u) : (k == ks ? br : 0u);
+        } else if (lane < 32) {
+            const int k = sd * S + j;
+            e = k < ks - 1 ? cur.c : (k == ks - 1 ? bl : 0u);
         }
-        const uint32_t up_tot = run;
-        run = 0;
+        uint32_t xu = e, xd = e;
+        xu = max(xu, dpp_u32<0x111>(xu, 0));  // row_shr:1
+        xu = max(xu, dpp_u32<0x112>(xu, 0));
+        xu = max(xu, dpp_u32<0x114>(xu, 0));
+        xu = max(xu, dpp_u32<0x118>(xu, 0));
+        xd = max(xd, dpp_u32<0x101>(xd, 0));  // row_shl:1
+        xd = max(xd, dpp_u32<0x102>(xd, 0));
+        xd = max(xd, dpp_u32<0x104>(xd, 0));
+        xd = max(xd, dpp_u32<0x108>(xd, 0));
+        const uint32_t up_s = (uint32_t)__builtin_amdgcn_readlane((int)xu, 15);
+        const uint32_t dn_s = (uint32_t)__builtin_amdgcn_readlane((int)xd, 16);
+        const uint32_t up_in =
+            wave_excl_max_up_u32(lane > su ? pre[S - 1] : (lane == su ? up_s : 0u), lane);
+        const uint32_t dn_in =
+            wave_excl_max_down_u32(lane < sd ? suf[0] : (lane == sd ? dn_s : 0u), lane);
+        const bool above = lane > su;
+        if (above || lane < sd) {
+            const uint32_t in = above ? up_in : dn_in;
 #pragma unroll
-        for (int q = S - 1; q >= 0; --q) {
-            const int k = k0 + q;
-            const uint32_t nxt = q + 1 < S ? g[q + 1] : gnx;
-            const uint32_t e = k < ks - 1 ? nxt : (k == ks - 1 ? bl : 0u);
-            run = max(run, e);
-            if (k < ks) loc[q] = run;
+            for (int q = 0; q < S; ++q) s_R[k0 + q] = max(above ? pre[q] : suf[q], in);
         }
-        const uint32_t dn_tot = run;
-        const uint32_t up_in = wave_excl_max_up_u32(up_tot, lane);
-        const uint32_t dn_in = wave_excl_max_down_u32(dn_tot, lane);
-#pragma unroll
-        for (int q = 0; q < S; ++q) {
-            const int k = k0 + q;
-            s_R[k] = max(loc[q], k >= ks ? up_in : dn_in);
-        }
+        if (lane < 16 && su < kWave && su * S + j >= ks) s_R[su * S + j] = xu;
+        if (lane >= 16 && lane < 32 && sd >= 0 && sd * S + j < ks) s_R[sd * S + j] = xd;
         wave_lds_sync();
 
         float* mrow = M + (size_t)i * (size_t)n + j0;

@@ -957,45 +957,46 @@ __device__ __forceinline__ int block256_excl_scan(int x, int* s, int* total) {
     return before + incl - x;
 }
 
-// group sizes and rank-tile counts per block
-__global__ __launch_bounds__(kScanThreads) void tree_scanpart_kernel(int n, const int32_t* gcount,
-                                                                    int32_t* bsum,
-                                                                    const int32_t* ctrl) {
+// Link-subtree sizes and the scans over the group sizes in one launch: blocks
+// [0, nsb) scan, blocks [nsb, nsb + nb) run tree_sizes_kernel's walk.  A scan
+// block of kScanThreads threads owns kScanBlock consecutive vertices (8 per
+// thread) and sums the group sizes and rank-tile counts of all vertices before
+// it itself (no other block is waited for).  It writes group starts, cleared
+// fill counters, rank-tile starts and owners; the last one records the number
+// of rank tiles.
+__global__ __launch_bounds__(kScanThreads) void tree_sizes_scan_kernel(
+    int n, int nsb, const int32_t* link, int32_t* size, const int32_t* gcount, int32_t* arrived,
+    int32_t* gstart, int32_t* gfill, int32_t* tstart, int32_t* owner, int32_t* ctrl) {
     __shared__ int s_a[8], s_b[8];
     if (!ctrl[C_ORDERED]) return;
-    const int b0 = blockIdx.x * kScanBlock + threadIdx.x * 8;
-    int s = 0, ts = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int m = b0 + j < n ? gcount[b0 + j] : 0;
+    if ((int)blockIdx.x >= nsb) {
+        const int v = ((int)blockIdx.x - nsb) * kScanThreads + threadIdx.x;
+        if (v == 0 || v >= n || gcount[v] != 0) return;
+        int x = v, sx = 1;
+        for (int guard = 0; guard < n; ++guard) {
+            const int p = link[x];
+            if (p <= 0) break;
+            __hip_atomic_fetch_add(&size[p], sx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int old = __hip_atomic_fetch_add(&arrived[p], 1, __ATOMIC_ACQ_REL,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+            if (old + 1 != gcount[p]) break;
+            sx = __hip_atomic_load(&size[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            x = p;
+        }
+        return;
+    }
+    const int blk0 = blockIdx.x * kScanBlock;
+    int pre = 0, tpre = 0;
+    for (int i = threadIdx.x; i < blk0; i += kScanThreads) {
+        const int m = gcount[i];
         const int nt = (m + kRankTile - 1) / kRankTile;
-        s += m;
-        ts += m > 1 ? nt * nt : 0;
+        pre += m;
+        tpre += m > 1 ? nt * nt : 0;
     }
-    int ta, tb;
-    (void)block256_excl_scan(s, s_a, &ta);
-    (void)block256_excl_scan(ts, s_b, &tb);
-    if (threadIdx.x == 0) {
-        bsum[2 * blockIdx.x] = ta;
-        bsum[2 * blockIdx.x + 1] = tb;
-    }
-}
-
-// group starts, cleared fill counters, rank-tile starts; the last block
-// records the number of rank tiles
-__global__ __launch_bounds__(kScanThreads) void tree_scan_kernel(int n, const int32_t* gcount,
-                                                                int32_t* gstart, int32_t* gfill,
-                                                                int32_t* tstart,
-                                                                const int32_t* bsum,
-                                                                int32_t* owner, int32_t* ctrl) {
-    __shared__ int s_a[8], s_b[8];
-    if (!ctrl[C_ORDERED]) return;
-    int run = 0, trun = 0;
-    for (int b = 0; b < (int)blockIdx.x; ++b) {
-        run += bsum[2 * b];
-        trun += bsum[2 * b + 1];
-    }
-    const int b0 = blockIdx.x * kScanBlock + threadIdx.x * 8;
+    int run, trun;
+    (void)block256_excl_scan(pre, s_a, &run);
+    (void)block256_excl_scan(tpre, s_b, &trun);
+    const int b0 = blk0 + threadIdx.x * 8;
     int m[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) m[j] = b0 + j < n ? gcount[b0 + j] : 0;
@@ -1022,7 +1023,7 @@ __global__ __launch_bounds__(kScanThreads) void tree_scan_kernel(int n, const in
             tr += m[j] > 1 ? nt * nt : 0;
         }
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) ctrl[C_TILES] = trun + tb;
+    if (blockIdx.x == nsb - 1 && threadIdx.x == 0) ctrl[C_TILES] = trun + tb;
 }
 
 __global__ __launch_bounds__(256) void tree_group_kernel(int n, const int32_t* link,
@@ -1109,62 +1110,32 @@ __global__ __launch_bounds__(256) void tree_place_kernel(int n, const int32_t* l
 }
 
 // Segmented exclusive scan of the placed sizes (segments = sibling groups)
-// -> total size of the smaller siblings of each slot, over the n-1 slots in
-// two grid launches like the scans above.  A block's summary is (sum after its
-// last segment head, whether it holds a head); a block's incoming carry sums
-// the summaries of the blocks before it back to the nearest one with a head.
+// -> total size of the smaller siblings of each slot, over the n-1 slots, one
+// launch: a block of kScanThreads threads owns kScanBlock consecutive slots;
+// its incoming carry is the sum of the sizes from the start of the group that
+// holds the slot before the block up to the block (read directly).
 __device__ __forceinline__ bool seg_head(const int32_t* grp, int i) {
     return i == 0 || grp[i] != grp[i - 1];
 }
 
-__global__ __launch_bounds__(kScanThreads) void tree_segpart_kernel(int n,
-                                                                   const int32_t* sorted_size,
-                                                                   const int32_t* sorted_grp,
-                                                                   int32_t* bseg,
-                                                                   const int32_t* ctrl) {
-    __shared__ int s_v[kScanThreads], s_h[kScanThreads];
-    if (!ctrl[C_ORDERED]) return;
-    const int m = n - 1;
-    const int b0 = blockIdx.x * kScanBlock + threadIdx.x * 8;
-    int tot = 0, head = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int i = b0 + j;
-        if (i < m) {
-            if (seg_head(sorted_grp, i)) {
-                tot = 0;
-                head = 1;
-            }
-            tot += sorted_size[i];
-        }
-    }
-    s_v[threadIdx.x] = tot;
-    s_h[threadIdx.x] = head;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int v = 0, h = 0;
-        for (int k = 0; k < kScanThreads; ++k) {
-            v = s_h[k] ? s_v[k] : v + s_v[k];
-            h |= s_h[k];
-        }
-        bseg[2 * blockIdx.x] = v;
-        bseg[2 * blockIdx.x + 1] = h;
-    }
-}
-
 __global__ __launch_bounds__(kScanThreads) void tree_segscan_kernel(
-    int n, const int32_t* sorted_size, const int32_t* sorted_grp, const int32_t* bseg,
+    int n, const int32_t* sorted_size, const int32_t* sorted_grp, const int32_t* gstart,
     int32_t* sorted_pre, const int32_t* ctrl) {
-    __shared__ int s_v[kScanThreads], s_h[kScanThreads];
+    __shared__ int s_v[kScanThreads], s_h[kScanThreads], s_a[8];
     if (!ctrl[C_ORDERED]) return;
     const int m = n - 1;
-    int carry = 0;
-    for (int b = (int)blockIdx.x - 1; b >= 0; --b) {
-        carry += bseg[2 * b];
-        if (bseg[2 * b + 1]) break;
-    }
     const int t = threadIdx.x;
-    const int b0 = blockIdx.x * kScanBlock + t * 8;
+    const int blk0 = blockIdx.x * kScanBlock;
+    int carry = 0;
+    {
+        int part = 0;
+        if (blk0 > 0 && blk0 <= m) {
+            const int st = gstart[sorted_grp[blk0 - 1]];
+            for (int i = st + t; i < blk0; i += kScanThreads) part += sorted_size[i];
+        }
+        (void)block256_excl_scan(part, s_a, &carry);
+    }
+    const int b0 = blk0 + t * 8;
     int sz[8];
     bool hd[8];
     int tot = 0, head = 0;
@@ -1387,19 +1358,11 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
     APPD_LAUNCH("tree_link_kernel", s,
         tree_link_kernel<<<nb, 256, 0, s>>>(n, w.keyup, w.link, w.gcount, w.ctrl));
     APPD_CHK();
-    APPD_LAUNCH("tree_sizes_kernel", s,
-        tree_sizes_kernel<<<nb, 256, 0, s>>>(n, w.link, w.size, w.gcount, w.hook, w.ctrl));
-    APPD_CHK();
-    // block summaries go to hx / hy (free in this phase): 2 * nsb <= max(n, 64)
-    // ints, the size of every per-vertex array of the workspace.  The rank-tile
-    // owners go to best (2n ints; at most (n/256 + 1)^2 <= 2n tiles).
+    // the rank-tile owners go to best (2n ints; at most (n/256 + 1)^2 <= 2n tiles)
     const int nsb = (n + kScanBlock - 1) / kScanBlock;
-    APPD_LAUNCH("tree_scanpart_kernel", s,
-        tree_scanpart_kernel<<<nsb, kScanThreads, 0, s>>>(n, w.gcount, w.hx, w.ctrl));
-    APPD_CHK();
-    APPD_LAUNCH("tree_scan_kernel", s,
-        tree_scan_kernel<<<nsb, kScanThreads, 0, s>>>(n, w.gcount, w.gstart, w.gfill, w.tstart,
-                                                      w.hx, (int32_t*)w.best, w.ctrl));
+    APPD_LAUNCH("tree_sizes_scan_kernel", s,
+        tree_sizes_scan_kernel<<<nsb + nb, kScanThreads, 0, s>>>(n, nsb, w.link, w.size, w.gcount,
+            w.hook, w.gstart, w.gfill, w.tstart, (int32_t*)w.best, w.ctrl));
     APPD_CHK();
     APPD_LAUNCH("tree_group_kernel", s,
         tree_group_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.gfill, w.grouped, w.rank,
@@ -1414,12 +1377,8 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
             w.sorted_grp, w.ctrl));
     APPD_CHK();
     const int nseg = max(1, (n - 1 + kScanBlock - 1) / kScanBlock);
-    APPD_LAUNCH("tree_segpart_kernel", s,
-        tree_segpart_kernel<<<nseg, kScanThreads, 0, s>>>(n, w.sorted_size, w.sorted_grp, w.hy,
-                                                          w.ctrl));
-    APPD_CHK();
     APPD_LAUNCH("tree_segscan_kernel", s,
-        tree_segscan_kernel<<<nseg, kScanThreads, 0, s>>>(n, w.sorted_size, w.sorted_grp, w.hy,
+        tree_segscan_kernel<<<nseg, kScanThreads, 0, s>>>(n, w.sorted_size, w.sorted_grp, w.gstart,
                                                           w.sorted_pre, w.ctrl));
     APPD_CHK();
     APPD_LAUNCH("tree_pos_kernel", s,

@@ -39,6 +39,7 @@ CSRC = "paper_2407_07058_amd/csrc/"
 KERNEL_SOURCES = {
     "fill_kernel": [CSRC + "appd_fill.h", CSRC + "appd_device.h", CSRC + "appd_single.hip"],
     "tree_pass_kernel": [CSRC + "appd_tree.hip", CSRC + "appd_device.h"],
+    "tree_refresh_kernel": [CSRC + "appd_tree.hip", CSRC + "appd_device.h"],
     "tree_rounds_kernel": [CSRC + "appd_tree.hip", CSRC + "appd_device.h"],
     "prim_single_kernel": [CSRC + "appd_prim.h", CSRC + "appd_device.h",
                            CSRC + "appd_single.hip"],
@@ -58,8 +59,10 @@ def alg_bytes_per_launch(kernel, n, launches=1.0, stats=None):
     }
     if kernel in per:
         return per[kernel]
-    if kernel == "tree_pass_kernel":         # W read once per pass that ran
-        return 4.0 * n * n * stats.get("passes", launches) / launches
+    if kernel == "tree_pass_kernel":         # the first pass: W read once, always runs
+        return 4.0 * n * n
+    if kernel == "tree_refresh_kernel":      # W read once per later pass that ran
+        return 4.0 * n * n * max(stats.get("passes", 1) - 1, 0) / launches
     if kernel == "tree_rounds_kernel":       # candidate lists (32 B per 4 entries) + labels
         return (8.0 * K_LIST + 12.0) * n * stats.get("passes", launches) / launches
     return None

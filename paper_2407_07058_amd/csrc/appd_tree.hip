@@ -79,19 +79,6 @@ __device__ __forceinline__ int ld_l2(const int32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// ---------------------------------------------------------------- init
-__global__ void tree_init_kernel(int n, int32_t* comp, uint64_t* best, uint64_t* lb,
-                                 int32_t* ctrl) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        comp[i] = i;
-        best[i] = kNone;
-        lb[i] = kNone;
-    }
-    if (i < 64) ctrl[i] = (i == C_NCOMP) ? n : 0;
-    if (i == 0 && n == 1) ctrl[C_DONE] = 1;
-}
-
 // ---------------------------------------------------------------- pass
 // One wave per row.  Lanes 0..K-1 hold the row's K smallest entries seen so
 // far, in ascending order; tau is the K-th.  The row is read in blocks of
@@ -107,18 +94,13 @@ __global__ void tree_init_kernel(int n, int32_t* comp, uint64_t* best, uint64_t*
 // VEC: rows are 16-byte aligned (n % 4 == 0), each lane reads 4 columns at once.
 constexpr int kPassElems = 32;
 
+// The pass over row u by one wave (u wave-uniform).
 template <bool WIDEST, bool FILTER, bool VEC>
-__global__ __launch_bounds__(kPassThreads) void tree_pass_kernel(const float* __restrict__ W,
-                                                                 int n,
-                                                                 const int32_t* __restrict__ comp,
-                                                                 int32_t* __restrict__ lptr,
-                                                                 uint32_t* __restrict__ groups,
-                                                                 int32_t* __restrict__ ctrl) {
-    if (ctrl[C_DONE] || (FILTER && ctrl[C_NCOMP] <= kCmat)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&ctrl[C_PASSES], 1);  // passes that ran
+__device__ __forceinline__ void pass_row(const float* __restrict__ W, int n,
+                                         const int32_t* __restrict__ comp,
+                                         int32_t* __restrict__ lptr,
+                                         uint32_t* __restrict__ groups, int u) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int u = blockIdx.x * (kPassThreads / kWave) + threadIdx.x / kWave;
-    if (u >= n) return;  // no barrier in this kernel
     const float* row = W + (size_t)u * (size_t)n;
     const int cu = FILTER ? comp[u] : u;
     uint64_t mine = kNone;    // this lane's slot of the sorted list (lanes < K)
@@ -218,9 +200,37 @@ __global__ __launch_bounds__(kPassThreads) void tree_pass_kernel(const float* __
     if (lane == 0) lptr[u] = 0;
 }
 
+// First pass over W (every row, no component filter).  It also sets up the
+// rounds' state, which nothing reads before the first rounds call: every
+// vertex its own component, empty minima, the control words.
+template <bool WIDEST, bool VEC>
+__global__ __launch_bounds__(kPassThreads) void tree_pass_kernel(const float* __restrict__ W,
+                                                                 int n, int32_t* __restrict__ comp,
+                                                                 uint64_t* __restrict__ best,
+                                                                 uint64_t* __restrict__ lb,
+                                                                 int32_t* __restrict__ lptr,
+                                                                 uint32_t* __restrict__ groups,
+                                                                 int32_t* __restrict__ ctrl) {
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * kPassThreads + t;
+    if (i < n) {
+        comp[i] = i;
+        best[i] = kNone;
+        lb[i] = kNone;
+    }
+    if (blockIdx.x == 0 && t < 64)
+        ctrl[t] = t == C_NCOMP ? n : (t == C_PASSES || (t == C_DONE && n == 1)) ? 1 : 0;
+    const int u = blockIdx.x * (kPassThreads / kWave) + t / kWave;
+    if (u >= n) return;  // no barrier in this kernel
+    pass_row<WIDEST, false, VEC>(W, n, nullptr, lptr, groups, u);
+}
+
 // ---------------------------------------------------------------- component table
-// Refresh pass for at most kCmat components (dense ids 0..C-1), computing the
-// smallest edge key between every pair of components.  By the cut property the
+// Refresh pass, one launch whose mode follows the number C of components left
+// (dense ids 0..C-1).  C > kCmat: the list pass again over every row, entries
+// inside the row's own component skipped (a persistent grid, one row per wave
+// at a time).  C <= kCmat: the component table, the smallest edge key between
+// every pair of components.  By the cut property the
 // spanning tree of the components under these minima is exactly the rest of
 // the minimum spanning tree.
 //
@@ -249,18 +259,24 @@ __device__ __forceinline__ void cmat_fold_slot(uint2* slot, float s, uint32_t v)
 }
 
 template <bool WIDEST, bool VEC>
-__global__ __launch_bounds__(kCmatThreads) void tree_cmat_kernel(const float* __restrict__ W,
-                                                                 int n,
-                                                                 const int32_t* __restrict__ comp,
-                                                                 uint64_t* __restrict__ part,
-                                                                 int32_t* __restrict__ ctrl) {
+__global__ __launch_bounds__(kCmatThreads) void tree_refresh_kernel(
+    const float* __restrict__ W, int n, const int32_t* __restrict__ comp,
+    int32_t* __restrict__ lptr, uint32_t* __restrict__ groups, uint64_t* __restrict__ part,
+    int32_t* __restrict__ ctrl) {
     constexpr int NW = kCmatThreads / kWave;
     __shared__ uint2 tab[NW][kCmat][kWave];
     __shared__ uint64_t pair[kCmat * kCmat];
     if (ctrl[C_DONE]) return;
     const int C = ctrl[C_NCOMP];
-    if (C > kCmat) return;
     const int t = threadIdx.x, lane = t & (kWave - 1), wid = t / kWave;
+    if (C > kCmat) {
+        // candidate lists again, entries inside the own component skipped
+        if (blockIdx.x == 0 && t == 0) atomicAdd(&ctrl[C_PASSES], 1);
+        const int u0 = __builtin_amdgcn_readfirstlane(blockIdx.x * NW + wid);
+        for (int u = u0; u < n; u += gridDim.x * NW)
+            pass_row<WIDEST, true, VEC>(W, n, comp, lptr, groups, u);
+        return;
+    }
     if (blockIdx.x == 0 && t == 0) {
         atomicAdd(&ctrl[C_PASSES], 1);
         ctrl[C_CMAT] = C;
@@ -1280,32 +1296,32 @@ static hipError_t launch_fallback(const float* W, int n, PrimOut out, int32_t* c
     return hipErrorInvalidValue;
 }
 
-template <bool WIDEST, bool FILTER>
-static void launch_pass(const float* W, int n, const TreeWs& w, hipStream_t s) {
+template <bool WIDEST>
+static void launch_first_pass(const float* W, int n, const TreeWs& w, hipStream_t s) {
     const int blocks = (n + kPassThreads / kWave - 1) / (kPassThreads / kWave);
     const bool vec = (n % 4 == 0) && (((uintptr_t)W & 15u) == 0);
     if (vec)
         APPD_LAUNCH("tree_pass_kernel", s,
-            tree_pass_kernel<WIDEST, FILTER, true><<<blocks, kPassThreads, 0, s>>>(W, n, w.comp,
-                w.lptr, (uint32_t*)w.lists, w.ctrl));
+            tree_pass_kernel<WIDEST, true><<<blocks, kPassThreads, 0, s>>>(W, n, w.comp, w.best,
+                w.lb, w.lptr, (uint32_t*)w.lists, w.ctrl));
     else
         APPD_LAUNCH("tree_pass_kernel", s,
-            tree_pass_kernel<WIDEST, FILTER, false><<<blocks, kPassThreads, 0, s>>>(W, n, w.comp,
-                w.lptr, (uint32_t*)w.lists, w.ctrl));
+            tree_pass_kernel<WIDEST, false><<<blocks, kPassThreads, 0, s>>>(W, n, w.comp, w.best,
+                w.lb, w.lptr, (uint32_t*)w.lists, w.ctrl));
 }
 
 template <bool WIDEST>
-static void launch_cmat(const float* W, int n, const TreeWs& w, hipStream_t s) {
+static void launch_refresh(const float* W, int n, const TreeWs& w, hipStream_t s) {
     const int blocks = kCmatBlocks(n);
     const bool vec = (n % 4 == 0) && (((uintptr_t)W & 15u) == 0);
     if (vec)
-        APPD_LAUNCH("tree_cmat_kernel", s,
-            tree_cmat_kernel<WIDEST, true><<<blocks, kCmatThreads, 0, s>>>(W, n, w.comp,
-                w.cmpart, w.ctrl));
+        APPD_LAUNCH("tree_refresh_kernel", s,
+            tree_refresh_kernel<WIDEST, true><<<blocks, kCmatThreads, 0, s>>>(W, n, w.comp,
+                w.lptr, (uint32_t*)w.lists, w.cmpart, w.ctrl));
     else
-        APPD_LAUNCH("tree_cmat_kernel", s,
-            tree_cmat_kernel<WIDEST, false><<<blocks, kCmatThreads, 0, s>>>(W, n, w.comp,
-                w.cmpart, w.ctrl));
+        APPD_LAUNCH("tree_refresh_kernel", s,
+            tree_refresh_kernel<WIDEST, false><<<blocks, kCmatThreads, 0, s>>>(W, n, w.comp,
+                w.lptr, (uint32_t*)w.lists, w.cmpart, w.ctrl));
 }
 
 template <bool WIDEST>
@@ -1316,9 +1332,6 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
     hipError_t e;
 #define APPD_CHK()                                     \
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    APPD_LAUNCH("tree_init_kernel", s,
-        tree_init_kernel<<<max(nb, 1), 256, 0, s>>>(n, w.comp, w.best, w.lb, w.ctrl));
-    APPD_CHK();
     const bool lds = n <= kMaxLdsN;
     const size_t vbytes = lds ? 4 * (size_t)n : 0;
     int cm = (int)((kLdsBytes - vbytes) / kTableBytes);
@@ -1333,13 +1346,10 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
     RoundArgs ra{W,      n,    w.comp, w.best, w.lb, w.lptr, (const uint32_t*)w.lists,
                  w.hook, w.hx, w.hy,   w.par,  w.ctrl, w.cmpart, cm};
     for (int p = 0; p < kPasses; ++p) {
-        if (p == 0) {
-            launch_pass<WIDEST, false>(W, n, w, s);
-        } else {  // candidate lists, or the component table once few are left
-            launch_pass<WIDEST, true>(W, n, w, s);
-            APPD_CHK();
-            launch_cmat<WIDEST>(W, n, w, s);
-        }
+        if (p == 0)
+            launch_first_pass<WIDEST>(W, n, w, s);
+        else  // candidate lists, or the component table once few are left
+            launch_refresh<WIDEST>(W, n, w, s);
         APPD_CHK();
         if (lds)
             APPD_LAUNCH("tree_rounds_kernel", s,

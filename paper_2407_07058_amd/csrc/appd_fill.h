@@ -33,18 +33,19 @@
 
 namespace appd {
 
-// Block prep: one workgroup (256 threads) per column block.  The block's
-// columns are sorted by attachment position (bitonic sort in LDS); then the gap
-// maxima are taken in one sweep over ek: position p (sp[k-1] < p <= sp[k])
-// belongs to slot k = the number of sorted positions below p, read off a bitmap
-// of those positions and its per-word prefix counts, and is folded into gap[k]
-// with an LDS atomic max.  ek is read coalesced, once per block.
-// Then the block's gap keys are sorted (bitonic, u64) and every slot k >= 1
-// gets its code for the fill: (2 * (rank of gap[k] among the block's gaps + 1))
-// << 11 | k, an order-preserving 32-bit stand-in for the key, together with the
-// decoded weight and flat index of gap[k] (decode tables indexed by k; entry 0
-// is the diagonal: 0.0, -1).  The sorted gaps are kept so that the fill can
-// code the two boundary keys of a row the same way.
+// Block prep: one workgroup (CB threads) per column block.  The block's
+// positions go into a bitmap over 0..n-1 with per-word prefix counts; the slot
+// of a column is the rank of its position read off them (the columns in
+// position order, without a sort).  The gap maxima are taken in one sweep over
+// ek: position p (sp[k-1] < p <= sp[k]) belongs to slot k = the number of the
+// block's positions below p, read off the same bitmap, and is folded into
+// gap[k] with an LDS atomic max.  ek is read coalesced, once per block.
+// Then the block's gap keys are sorted (bitonic, u64, one per thread) and every
+// slot k >= 1 gets its code for the fill: (2 * (rank of gap[k] among the
+// block's gaps + 1)) << 11 | k, an order-preserving 32-bit stand-in for the
+// key, together with the decoded weight and flat index of gap[k] (decode
+// tables indexed by k; entry 0 is the diagonal: 0.0, -1).  The sorted gaps are
+// kept so that the fill can code the two boundary keys of a row the same way.
 // LDS: keys CB words; bits and prefix (n + 31) / 32 words each; gap and srt CB
 // keys each.
 constexpr int kCodeShift = 11;  // slot codes below 2^11 (CB + boundary entries)
@@ -65,35 +66,13 @@ __device__ __forceinline__ void fill_prep_block(const int32_t* __restrict__ pos,
     const int j0 = blk * CB;
     const int cnt = min(CB, n - j0);
     const int nw = (n + 31) / 32;
-    for (int c = threadIdx.x; c < CB; c += blockDim.x) {
-        keys[c] = c < cnt ? (((uint32_t)pos[j0 + c] << 16) | (uint32_t)c) : 0xffffffffu;
-        gap[c] = 0;
-    }
+    for (int c = threadIdx.x; c < CB; c += blockDim.x) gap[c] = 0;
     for (int w = threadIdx.x; w < nw; w += blockDim.x) bits[w] = 0;
     __syncthreads();
-    // bitonic sort, ascending
-    for (int size = 2; size <= CB; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < CB / 2; i += blockDim.x) {
-                const int lo = 2 * i - (i & (stride - 1));
-                const int hi = lo + stride;
-                const bool asc = (lo & size) == 0;
-                const uint32_t x = keys[lo], y = keys[hi];
-                if ((x > y) == asc) {
-                    keys[lo] = y;
-                    keys[hi] = x;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
-        const uint32_t kk = keys[k];
-        const int sp = (int)(kk >> 16);
-        const int col = (int)(kk & 0xffffu);
-        blk_sp[j0 + k] = (uint16_t)sp;
-        blk_slot[j0 + col] = (uint16_t)k;
-        atomicOr(&bits[sp >> 5], 1u << (sp & 31));
+    // the block's positions as a bitmap over 0..n-1
+    for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+        const int p = pos[j0 + c];
+        atomicOr(&bits[p >> 5], 1u << (p & 31));
     }
     __syncthreads();
     // exclusive prefix of the word counts (one thread per run of words)
@@ -118,6 +97,15 @@ __device__ __forceinline__ void fill_prep_block(const int32_t* __restrict__ pos,
         run += __popc(bits[w]);
     }
     __syncthreads();
+    // slot of column c = rank of its position among the block's positions
+    for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+        const int p = pos[j0 + c];
+        const int k = wpre[p >> 5] + __popc(bits[p >> 5] & ((1u << (p & 31)) - 1u));
+        keys[k] = ((uint32_t)p << 16) | (uint32_t)c;
+        blk_sp[j0 + k] = (uint16_t)p;
+        blk_slot[j0 + c] = (uint16_t)k;
+    }
+    __syncthreads();
     // one sweep over ek: position p > sp[0] lies in slot k = #{sp < p}
     const int lo = (int)(keys[0] >> 16) + 1, hi = (int)(keys[cnt - 1] >> 16);
     for (int p = lo + (int)threadIdx.x; p <= hi; p += blockDim.x) {
@@ -125,24 +113,31 @@ __device__ __forceinline__ void fill_prep_block(const int32_t* __restrict__ pos,
         atomicMax((unsigned long long*)&gap[k], (unsigned long long)ek[p]);
     }
     __syncthreads();
-    // sorted gaps (slots 1..cnt-1), padded with the largest key
-    for (int k = threadIdx.x; k < CB; k += blockDim.x) srt[k] = (k + 1 < cnt) ? gap[k + 1] : ~0ull;
-    __syncthreads();
-    for (int size = 2; size <= CB; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < CB / 2; i += blockDim.x) {
-                const int lo = 2 * i - (i & (stride - 1));
-                const int hi = lo + stride;
-                const bool asc = (lo & size) == 0;
-                const uint64_t x = srt[lo], y = srt[hi];
-                if ((x > y) == asc) {
-                    srt[lo] = y;
-                    srt[hi] = x;
+    // sorted gaps (slots 1..cnt-1), padded with the largest key: bitonic sort
+    // with one key per thread (blockDim.x == CB); exchanges at strides below
+    // the wave width go through shuffles, the others through LDS
+    {
+        const int t = threadIdx.x;
+        uint64_t x = (t + 1 < cnt) ? gap[t + 1] : ~0ull;
+        for (int size = 2; size <= CB; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                uint64_t y;
+                if (stride >= kWave) {
+                    srt[t] = x;
+                    __syncthreads();
+                    y = srt[t ^ stride];
+                    __syncthreads();
+                } else {
+                    y = shfl_xor_u64(x, stride);
                 }
+                const bool up = (t & size) == 0;
+                const bool lower = (t & stride) == 0;
+                x = (lower == up) ? umin64(x, y) : umax64(x, y);
             }
-            __syncthreads();
         }
+        srt[t] = x;
     }
+    __syncthreads();
     for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
         uint32_t code = 0;
         float dm = 0.0f;

@@ -24,6 +24,7 @@ template <int CB, bool WIDEST>
 __global__ __launch_bounds__(kPrepThreads) void fill_prep_kernel(const int32_t* __restrict__ pos,
                                                                  const uint64_t* __restrict__ ek,
                                                                  int n, SingleWs w) {
+    static_assert(kPrepThreads == CB, "the gap sort keeps one key per thread");
     __shared__ uint32_t keys[CB];
     __shared__ uint32_t bits[(APPD_MAX_N + 31) / 32];
     __shared__ int32_t wpre[(APPD_MAX_N + 31) / 32];

@@ -287,26 +287,37 @@ __global__ __launch_bounds__(kCmatThreads) void tree_refresh_kernel(
 #pragma unroll
     for (int c = 0; c < kCmat; ++c) col[c * kWave] = empty;
     __syncthreads();
-    const int nw = gridDim.x * NW;
-    for (int u = blockIdx.x * NW + wid; u < n; u += nw) {
+    // W is symmetric: row u offers only its columns v > u, so edge (u, v) lands
+    // under the component of its smaller endpoint (the rounds take the minimum
+    // of both orientations).  A wave takes rows q and n - 1 - q together, which
+    // makes every wave's share n - 1 columns.
+    auto row_minima = [&](int u) {
         const float* row = W + (size_t)u * (size_t)n;
         const int cu = comp[u] & (kCmat - 1);
         if (VEC) {
-            float4 x = *(const float4*)(row + (lane * 4 < n ? lane * 4 : 0));
-            int4 c4 = *(const int4*)(comp + (lane * 4 < n ? lane * 4 : 0));
-            for (int c0 = lane * 4; c0 < n; c0 += kWave * 4) {
-                const int c1 = c0 + kWave * 4 < n ? c0 + kWave * 4 : c0;  // prefetch
+            const int base = (u + 1) & ~3;  // 16-byte aligned; columns <= u skipped
+            int c0 = base + lane * 4;
+            float4 x = *(const float4*)(row + min(c0, n - 4));
+            int4 c4 = *(const int4*)(comp + min(c0, n - 4));
+            for (; c0 < n; c0 += kWave * 4) {
+                const int c1 = min(c0 + kWave * 4, n - 4);  // prefetch
                 const float4 xn = *(const float4*)(row + c1);
                 const int4 cn = *(const int4*)(comp + c1);
-                cmat_fold_slot(&col[(c4.x & (kCmat - 1)) * kWave], WIDEST ? -x.x : x.x, c0);
-                cmat_fold_slot(&col[(c4.y & (kCmat - 1)) * kWave], WIDEST ? -x.y : x.y, c0 + 1);
-                cmat_fold_slot(&col[(c4.z & (kCmat - 1)) * kWave], WIDEST ? -x.z : x.z, c0 + 2);
+                if (c0 > u) {
+                    cmat_fold_slot(&col[(c4.x & (kCmat - 1)) * kWave], WIDEST ? -x.x : x.x, c0);
+                }
+                if (c0 + 1 > u) {
+                    cmat_fold_slot(&col[(c4.y & (kCmat - 1)) * kWave], WIDEST ? -x.y : x.y, c0 + 1);
+                }
+                if (c0 + 2 > u) {
+                    cmat_fold_slot(&col[(c4.z & (kCmat - 1)) * kWave], WIDEST ? -x.z : x.z, c0 + 2);
+                }
                 cmat_fold_slot(&col[(c4.w & (kCmat - 1)) * kWave], WIDEST ? -x.w : x.w, c0 + 3);
                 x = xn;
                 c4 = cn;
             }
         } else {
-            for (int c = lane; c < n; c += kWave) {
+            for (int c = u + 1 + lane; c < n; c += kWave) {
                 const float x = row[c];
                 cmat_fold_slot(&col[(comp[c] & (kCmat - 1)) * kWave], WIDEST ? -x : x, c);
             }
@@ -327,6 +338,12 @@ __global__ __launch_bounds__(kCmatThreads) void tree_refresh_kernel(
         for (int c2 = 0; c2 < kCmat; ++c2) col[c2 * kWave] = empty;
         if (lane < kCmat && m != kNone)
             atomicMin((unsigned long long*)&pair[cu * kCmat + c], (unsigned long long)m);
+    };
+    const int nw = gridDim.x * NW;
+    const int npairs = (n + 1) / 2;
+    for (int q = __builtin_amdgcn_readfirstlane(blockIdx.x * NW + wid); q < npairs; q += nw) {
+        row_minima(q);
+        if (n - 1 - q != q) row_minima(n - 1 - q);
     }
     __syncthreads();
     if (t < kCmat * kCmat) part[(size_t)blockIdx.x * kCmat * kCmat + t] = pair[t];
@@ -480,6 +497,12 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
         }
         __syncthreads();
         atomicMin((unsigned long long*)&s_cm[e], (unsigned long long)m);
+        __syncthreads();
+        // an edge was recorded under its smaller endpoint's component only
+        uint64_t sym = kNone;
+        if (t < kCmat * kCmat) sym = umin64(s_cm[t], s_cm[(t % kCmat) * kCmat + t / kCmat]);
+        __syncthreads();
+        if (t < kCmat * kCmat) s_cm[t] = sym;
         __syncthreads();
     }
     if (LDS && first && !ctrl[C_DONE]) {

@@ -485,7 +485,9 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
         const int nparts = kCmatBlocks(n);
         if (t < kCmat * kCmat) s_cm[t] = kNone;
         uint64_t m = kNone;
-        for (int g0 = q; g0 < nparts; g0 += 4 * 8) {
+        // only entries between the c0 components are ever set
+        const bool used = e / kCmat < c0 && e % kCmat < c0;
+        for (int g0 = q; used && g0 < nparts; g0 += 4 * 8) {
             uint64_t v[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {

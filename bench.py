@@ -61,8 +61,10 @@ def alg_bytes_per_launch(kernel, n, launches=1.0, stats=None):
         return per[kernel]
     if kernel == "tree_pass_kernel":         # the first pass: W read once, always runs
         return 4.0 * n * n
-    if kernel == "tree_refresh_kernel":      # W read once per later pass that ran
-        return 4.0 * n * n * max(stats.get("passes", 1) - 1, 0) / launches
+    if kernel == "tree_refresh_kernel":      # later passes that ran: a list pass reads W,
+        tables = stats.get("tables", 0)      # a component-table pass its upper triangle
+        lists = max(stats.get("passes", 1) - 1 - tables, 0)
+        return (4.0 * n * n * lists + 2.0 * n * (n - 1) * tables) / launches
     if kernel == "tree_rounds_kernel":       # candidate lists (32 B per 4 entries) + labels
         return (8.0 * K_LIST + 12.0) * n * stats.get("passes", launches) / launches
     return None

@@ -113,7 +113,9 @@ int appd_tree(const float* W, int n, int mode, int32_t* order, int32_t* parent, 
 /* What the last spanning-tree run in ws did (for measurement): stats[0] = 1 if
  * the Boruvka path ran (else Prim's algorithm, and the rest are 0), stats[1] =
  * passes over W, stats[2] = Boruvka rounds, stats[3] = 1 if it fell back to
- * Prim.  n and mode as in that run.  Synchronises `stream`. */
+ * Prim, stats[4] = how many of the passes were component-table passes (those
+ * read only the upper triangle of W).  stats holds 5 entries.  n and mode as
+ * in that run.  Synchronises `stream`. */
 int appd_tree_stats(int n, int mode, const void* ws, size_t ws_bytes, int32_t* stats,
                     void* stream);
 int appd_fill(int n, int mode, const void* ws, size_t ws_bytes, float* M, int32_t* idx,

@@ -176,12 +176,14 @@ def forward(W: torch.Tensor, mode: int = MINIMAX, return_tree: bool = False, out
 
 def tree_stats(n: int, workspace: torch.Tensor, mode: int = MINIMAX, tree: str = "auto") -> dict:
     """What the last spanning-tree run in `workspace` did: Boruvka or Prim,
-    passes over W, Boruvka rounds, fallback to Prim."""
-    st = (ctypes.c_int32 * 4)()
+    passes over W (of which `tables` were component-table passes over its
+    upper triangle), Boruvka rounds, fallback to Prim."""
+    st = (ctypes.c_int32 * 5)()
     _check(lib().appd_tree_stats(int(n), _mode(mode, tree), _ptr(workspace), workspace.numel(),
                                  ctypes.cast(st, ctypes.c_void_p), _stream(workspace.device)),
            "appd_tree_stats")
-    return {"boruvka": bool(st[0]), "passes": st[1], "rounds": st[2], "fallback": bool(st[3])}
+    return {"boruvka": bool(st[0]), "passes": st[1], "rounds": st[2], "fallback": bool(st[3]),
+            "tables": st[4]}
 
 
 def linkage(W: torch.Tensor, mode: int = MINIMAX, tree: str = "auto",

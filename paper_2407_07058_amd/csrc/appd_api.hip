@@ -118,11 +118,11 @@ int appd_tree_stats(int n, int mode, const void* ws, size_t ws_bytes, int32_t* s
     const bool parallel =
         algo == APPD_TREE_BORUVKA || (algo == APPD_TREE_AUTO && n >= appd::parallel_tree_min_n());
     stats[0] = parallel ? 1 : 0;
-    stats[1] = stats[2] = stats[3] = 0;
+    stats[1] = stats[2] = stats[3] = stats[4] = 0;
     if (!parallel || n < 2) return ok();
     appd::SingleWs w = appd::carve_single(const_cast<void*>(ws), n);
-    if (appd::tree_stats(w.tree_ws, n, &stats[1], &stats[2], &stats[3], (hipStream_t)stream) !=
-        hipSuccess) {
+    if (appd::tree_stats(w.tree_ws, n, &stats[1], &stats[2], &stats[3], &stats[4],
+                         (hipStream_t)stream) != hipSuccess) {
         (void)hipGetLastError();
         return fail(APPD_EHIP);
     }

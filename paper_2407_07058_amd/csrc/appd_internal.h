@@ -44,7 +44,7 @@ struct PrimOut;
 hipError_t run_tree_parallel(const float* W, int n, int mode, const PrimOut& out, void* tws,
                              hipStream_t s);
 hipError_t tree_stats(const void* tws, int n, int32_t* passes, int32_t* rounds, int32_t* fallback,
-                      hipStream_t s);
+                      int32_t* tables, hipStream_t s);
 hipError_t run_linkage(const float* W, int n, int mode, const PrimOut& out, void* tws, double* Z,
                        hipStream_t s);
 bool valid_mode(int mode);

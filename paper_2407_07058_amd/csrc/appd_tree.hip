@@ -56,7 +56,7 @@ constexpr int kGroupWords = 8;
 
 // control block (int32 words); word 32 holds the number of rank tiles
 enum { C_DONE = 0, C_NCOMP, C_NEED_PASS, C_FALLBACK, C_ROUNDS, C_ORDERED, C_PASSES, C_CMAT,
-       C_WORDS };
+       C_TABLES, C_WORDS };  // C_TABLES: component-table passes that ran
 // With at most kCmat components left, a refresh pass computes the smallest
 // edge key between every pair of components instead of candidate lists
 // (C_CMAT = the number of components it saw); the next rounds call then
@@ -279,6 +279,7 @@ __global__ __launch_bounds__(kCmatThreads) void tree_refresh_kernel(
     }
     if (blockIdx.x == 0 && t == 0) {
         atomicAdd(&ctrl[C_PASSES], 1);
+        atomicAdd(&ctrl[C_TABLES], 1);
         ctrl[C_CMAT] = C;
     }
     if (t < kCmat * kCmat) pair[t] = kNone;
@@ -1570,7 +1571,7 @@ namespace appd {
 // Passes over W and Boruvka rounds the last parallel-tree run used, and
 // whether it fell back to sequential Prim (read from the control words).
 hipError_t tree_stats(const void* tws, int n, int32_t* passes, int32_t* rounds, int32_t* fallback,
-                      hipStream_t s) {
+                      int32_t* tables, hipStream_t s) {
     TreeWs w = carve_tree(const_cast<void*>(tws), n);
     int32_t c[C_WORDS];
     hipError_t e = hipMemcpyAsync(c, w.ctrl, sizeof(c), hipMemcpyDeviceToHost, s);
@@ -1579,6 +1580,7 @@ hipError_t tree_stats(const void* tws, int n, int32_t* passes, int32_t* rounds, 
     *passes = c[C_PASSES];
     *rounds = c[C_ROUNDS];
     *fallback = c[C_FALLBACK];
+    *tables = c[C_TABLES];
     return hipSuccess;
 }
 }  // namespace appd

@@ -133,4 +133,4 @@ def test_boruvka_component_table(k, mode):
     Mo, io = ref(W)
     assert np.array_equal(M.cpu().numpy().view(np.uint32), Mo.view(np.uint32))
     assert np.array_equal(idx.cpu().numpy(), io)
-    assert st["boruvka"] and not st["fallback"] and st["passes"] >= 1, st
+    assert st["boruvka"] and not st["fallback"] and st["tables"] >= 1, st

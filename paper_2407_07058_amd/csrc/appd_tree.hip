@@ -786,7 +786,9 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
                 if (small) t_best[d] = t_lb[d] = kNone;
                 else a.best[d] = a.lb[d] = kNone;
             }
-            if (pending > 0) {  // lists still being walked: another round
+            // lists still being walked: another round, unless the component
+            // table can take over (at most kCmat components left)
+            if (pending > 0 && C > kCmat) {
                 __syncthreads();
                 continue;
             }

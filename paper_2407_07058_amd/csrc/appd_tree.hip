@@ -895,7 +895,7 @@ __global__ __launch_bounds__(256) void tree_keyup_kernel(const float* __restrict
                                                         const int32_t* par, uint64_t* keyup,
                                                         int32_t* link, int32_t* size,
                                                         int32_t* gcount, int32_t* arrived,
-                                                        const int32_t* ctrl) {
+                                                        uint64_t* sa, const int32_t* ctrl) {
     if (!ctrl[C_ORDERED]) return;
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
@@ -907,6 +907,7 @@ __global__ __launch_bounds__(256) void tree_keyup_kernel(const float* __restrict
     size[v] = 1;
     gcount[v] = 0;
     arrived[v] = 0;
+    if (sa) sa[v] = 1ull << 32;  // packed (size, arrivals): size 1, none arrived
 }
 
 // arr[target] += 1 for every active lane.  Lanes aiming at vertex 0 (the
@@ -1002,29 +1003,32 @@ __device__ __forceinline__ int block256_excl_scan(int x, int* s, int* total) {
 }
 
 // Link-subtree sizes and the scans over the group sizes in one launch: blocks
-// [0, nsb) scan, blocks [nsb, nsb + nb) run tree_sizes_kernel's walk.  A scan
+// [0, nsb) scan, blocks [nsb, nsb + nb) run tree_sizes_kernel's walk on packed
+// words sa[x] = size << 32 | arrivals: one atomic per step adds a child's size
+// and its arrival, and the child that completes the count reads x's final size
+// from the value it returns.  A scan
 // block of kScanThreads threads owns kScanBlock consecutive vertices (8 per
 // thread) and sums the group sizes and rank-tile counts of all vertices before
 // it itself (no other block is waited for).  It writes group starts, cleared
 // fill counters, rank-tile starts and owners; the last one records the number
 // of rank tiles.
 __global__ __launch_bounds__(kScanThreads) void tree_sizes_scan_kernel(
-    int n, int nsb, const int32_t* link, int32_t* size, const int32_t* gcount, int32_t* arrived,
-    int32_t* gstart, int32_t* gfill, int32_t* tstart, int32_t* owner, int32_t* ctrl) {
+    int n, int nsb, const int32_t* link, uint64_t* sa, const int32_t* gcount, int32_t* gstart,
+    int32_t* gfill, int32_t* tstart, int32_t* owner, int32_t* ctrl) {
     __shared__ int s_a[8], s_b[8];
     if (!ctrl[C_ORDERED]) return;
     if ((int)blockIdx.x >= nsb) {
         const int v = ((int)blockIdx.x - nsb) * kScanThreads + threadIdx.x;
         if (v == 0 || v >= n || gcount[v] != 0) return;
-        int x = v, sx = 1;
+        int x = v;
+        uint32_t sx = 1;
         for (int guard = 0; guard < n; ++guard) {
             const int p = link[x];
             if (p <= 0) break;
-            __hip_atomic_fetch_add(&size[p], sx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int old = __hip_atomic_fetch_add(&arrived[p], 1, __ATOMIC_ACQ_REL,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-            if (old + 1 != gcount[p]) break;
-            sx = __hip_atomic_load(&size[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t old = __hip_atomic_fetch_add(&sa[p], ((uint64_t)sx << 32) | 1ull,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((int)(uint32_t)old + 1 != gcount[p]) break;
+            sx += (uint32_t)(old >> 32);
             x = p;
         }
         return;
@@ -1141,7 +1145,7 @@ __global__ __launch_bounds__(kRankTile) void tree_rank_kernel(int n, const int32
 // Each vertex's link-subtree size at (group start + rank): siblings in key order.
 __global__ __launch_bounds__(256) void tree_place_kernel(int n, const int32_t* link,
                                                         const int32_t* gstart,
-                                                        const int32_t* rank, const int32_t* size,
+                                                        const int32_t* rank, const uint64_t* sa,
                                                         int32_t* sorted_size, int32_t* sorted_grp,
                                                         const int32_t* ctrl) {
     if (!ctrl[C_ORDERED]) return;
@@ -1149,7 +1153,7 @@ __global__ __launch_bounds__(256) void tree_place_kernel(int n, const int32_t* l
     if (v == 0 || v >= n) return;
     const int g = link[v];
     const int slot = gstart[g] + rank[v];
-    sorted_size[slot] = size[v];
+    sorted_size[slot] = (int32_t)(sa[v] >> 32);
     sorted_grp[slot] = g;
 }
 
@@ -1391,16 +1395,17 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
     if (e != hipSuccess) return e;
     APPD_LAUNCH("tree_keyup_kernel", s,
         tree_keyup_kernel<WIDEST><<<nb, 256, 0, s>>>(W, n, w.par, w.keyup, w.link, w.size, w.gcount,
-            w.hook, w.ctrl));
+            w.hook, w.lb, w.ctrl));
     APPD_CHK();
     APPD_LAUNCH("tree_link_kernel", s,
         tree_link_kernel<<<nb, 256, 0, s>>>(n, w.keyup, w.link, w.gcount, w.ctrl));
     APPD_CHK();
-    // the rank-tile owners go to best (2n ints; at most (n/256 + 1)^2 <= 2n tiles)
+    // the packed (size, arrivals) words go to lb and the rank-tile owners to
+    // best (2n ints; at most (n/256 + 1)^2 <= 2n tiles): both are free by now
     const int nsb = (n + kScanBlock - 1) / kScanBlock;
     APPD_LAUNCH("tree_sizes_scan_kernel", s,
-        tree_sizes_scan_kernel<<<nsb + nb, kScanThreads, 0, s>>>(n, nsb, w.link, w.size, w.gcount,
-            w.hook, w.gstart, w.gfill, w.tstart, (int32_t*)w.best, w.ctrl));
+        tree_sizes_scan_kernel<<<nsb + nb, kScanThreads, 0, s>>>(n, nsb, w.link, w.lb, w.gcount,
+            w.gstart, w.gfill, w.tstart, (int32_t*)w.best, w.ctrl));
     APPD_CHK();
     APPD_LAUNCH("tree_group_kernel", s,
         tree_group_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.gfill, w.grouped, w.rank,
@@ -1411,7 +1416,7 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
             (const int32_t*)w.best, w.grouped, w.keyup, w.rank, w.ctrl));
     APPD_CHK();
     APPD_LAUNCH("tree_place_kernel", s,
-        tree_place_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.rank, w.size, w.sorted_size,
+        tree_place_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.rank, w.lb, w.sorted_size,
             w.sorted_grp, w.ctrl));
     APPD_CHK();
     const int nseg = max(1, (n - 1 + kScanBlock - 1) / kScanBlock);
@@ -1531,11 +1536,11 @@ hipError_t run_linkage(const float* W, int n, int mode, const PrimOut& out, void
     if (widest)
         APPD_LAUNCH("tree_keyup_kernel", s,
             tree_keyup_kernel<true><<<nb, 256, 0, s>>>(W, n, out.parent, w.keyup, w.link, w.size,
-                w.gcount, w.hook, w.ctrl));
+                w.gcount, w.hook, nullptr, w.ctrl));
     else
         APPD_LAUNCH("tree_keyup_kernel", s,
             tree_keyup_kernel<false><<<nb, 256, 0, s>>>(W, n, out.parent, w.keyup, w.link, w.size,
-                w.gcount, w.hook, w.ctrl));
+                w.gcount, w.hook, nullptr, w.ctrl));
     APPD_CHK_L();
     APPD_LAUNCH("tree_link_kernel", s,
         tree_link_kernel<<<nb, 256, 0, s>>>(n, w.keyup, w.link, w.gcount, w.ctrl));

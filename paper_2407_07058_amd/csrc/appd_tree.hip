@@ -1010,11 +1010,11 @@ __device__ __forceinline__ int block256_excl_scan(int x, int* s, int* total) {
 // block of kScanThreads threads owns kScanBlock consecutive vertices (8 per
 // thread) and sums the group sizes and rank-tile counts of all vertices before
 // it itself (no other block is waited for).  It writes group starts, cleared
-// fill counters, rank-tile starts and owners; the last one records the number
+// fill counters and rank-tile starts; the last one records the number
 // of rank tiles.
 __global__ __launch_bounds__(kScanThreads) void tree_sizes_scan_kernel(
     int n, int nsb, const int32_t* link, uint64_t* sa, const int32_t* gcount, int32_t* gstart,
-    int32_t* gfill, int32_t* tstart, int32_t* owner, int32_t* ctrl) {
+    int32_t* gfill, int32_t* tstart, int32_t* ctrl) {
     __shared__ int s_a[8], s_b[8];
     if (!ctrl[C_ORDERED]) return;
     if ((int)blockIdx.x >= nsb) {
@@ -1033,13 +1033,20 @@ __global__ __launch_bounds__(kScanThreads) void tree_sizes_scan_kernel(
         }
         return;
     }
-    const int blk0 = blockIdx.x * kScanBlock;
+    const int blk0 = blockIdx.x * kScanBlock;  // a multiple of 4 * kScanThreads
     int pre = 0, tpre = 0;
-    for (int i = threadIdx.x; i < blk0; i += kScanThreads) {
-        const int m = gcount[i];
+    auto count = [&](int m) {
         const int nt = (m + kRankTile - 1) / kRankTile;
         pre += m;
         tpre += m > 1 ? nt * nt : 0;
+    };
+#pragma unroll 4
+    for (int i = 4 * threadIdx.x; i < blk0; i += 4 * kScanThreads) {  // 16-byte loads
+        const int4 m = *(const int4*)(gcount + i);
+        count(m.x);
+        count(m.y);
+        count(m.z);
+        count(m.w);
     }
     int run, trun;
     (void)block256_excl_scan(pre, s_a, &run);
@@ -1066,46 +1073,56 @@ __global__ __launch_bounds__(kScanThreads) void tree_sizes_scan_kernel(
             gfill[b0 + j] = 0;
             tstart[b0 + j] = tr;
             r += m[j];
-            if (m[j] > 1)  // rank tiles of this group belong to it
-                for (int k = 0; k < nt * nt; ++k) owner[tr + k] = b0 + j;
             tr += m[j] > 1 ? nt * nt : 0;
         }
     }
     if (blockIdx.x == nsb - 1 && threadIdx.x == 0) ctrl[C_TILES] = trun + tb;
 }
 
-__global__ __launch_bounds__(256) void tree_group_kernel(int n, const int32_t* link,
-                                                        const int32_t* gstart, int32_t* gfill,
-                                                        int32_t* grouped, int32_t* rank,
-                                                        const int32_t* ctrl) {
+constexpr int kGroupThreads = 1024;
+
+__global__ __launch_bounds__(kGroupThreads) void tree_group_kernel(int n, const int32_t* link,
+                                                                  const int32_t* gstart,
+                                                                  int32_t* gfill, int32_t* grouped,
+                                                                  int32_t* rank,
+                                                                  const int32_t* ctrl) {
+    constexpr int NW = kGroupThreads / kWave;
+    __shared__ int s_w0[NW];
+    __shared__ int s_base0;
     if (!ctrl[C_ORDERED]) return;
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v == 0 || v >= n) return;
-    const int g = link[v];
-    // lanes of the same group as the first active lane, or of vertex 0's group,
-    // take consecutive slots from one atomic
-    const int lane = threadIdx.x & (kWave - 1);
-    const int lead = __builtin_amdgcn_readfirstlane(g);
-    const uint64_t ml = __ballot(g == lead);
-    const uint64_t m0 = lead == 0 ? 0ull : __ballot(g == 0);
-    int slot = 0;
-    if (m0) {
-        const int first = __ffsll((unsigned long long)m0) - 1;
-        int b = 0;
-        if (lane == first) b = atomicAdd(&gfill[0], __popcll(m0));
-        b = __builtin_amdgcn_readlane(b, first);
-        if (g == 0) slot = b + __popcll(m0 & ((1ull << lane) - 1));
+    const int t = threadIdx.x, lane = t & (kWave - 1), wid = t / kWave;
+    const int v = blockIdx.x * kGroupThreads + t;
+    const bool act = v > 0 && v < n;
+    const int g = act ? link[v] : -1;
+    // vertex 0's group (by far the largest): one atomic per workgroup
+    const uint64_t m0 = __ballot(g == 0);
+    if (lane == 0) s_w0[wid] = __popcll(m0);
+    __syncthreads();
+    if (t == 0) {
+        int tot = 0;
+        for (int w = 0; w < NW; ++w) tot += s_w0[w];
+        s_base0 = tot ? atomicAdd(&gfill[0], tot) : 0;
     }
-    {
-        const int first = __ffsll((unsigned long long)ml) - 1;
-        int b = 0;
-        if (lane == first) b = atomicAdd(&gfill[lead], __popcll(ml));
-        b = __builtin_amdgcn_readlane(b, first);
-        if (g == lead) slot = b + __popcll(ml & ((1ull << lane) - 1));
-    }
-    if (g != lead && g != 0) slot = atomicAdd(&gfill[g], 1);
-    grouped[gstart[g] + slot] = v;
+    __syncthreads();
+    if (!act) return;
     rank[v] = 0;
+    int slot;
+    if (g == 0) {
+        int before = s_base0;
+        for (int w = 0; w < wid; ++w) before += s_w0[w];
+        slot = before + __popcll(m0 & ((1ull << lane) - 1));
+    } else {
+        // lanes of the first other lane's group take consecutive slots from one atomic
+        const uint64_t rest = __ballot(g != 0);
+        const int first = __ffsll((unsigned long long)rest) - 1;
+        const int lead = __builtin_amdgcn_readlane(g, first);
+        const uint64_t ml = __ballot(g == lead);
+        int bl = 0;
+        if (lane == first) bl = atomicAdd(&gfill[lead], __popcll(ml));
+        bl = __builtin_amdgcn_readlane(bl, first);
+        slot = g == lead ? bl + __popcll(ml & ((1ull << lane) - 1)) : atomicAdd(&gfill[g], 1);
+    }
+    grouped[gstart[g] + slot] = v;
 }
 
 // Rank among siblings: tile (group, v-block, member-block) counts the members
@@ -1113,7 +1130,6 @@ __global__ __launch_bounds__(256) void tree_group_kernel(int n, const int32_t* l
 __global__ __launch_bounds__(kRankTile) void tree_rank_kernel(int n, const int32_t* gcount,
                                                              const int32_t* gstart,
                                                              const int32_t* tstart,
-                                                             const int32_t* owner,
                                                              const int32_t* grouped,
                                                              const uint64_t* keyup, int32_t* rank,
                                                              const int32_t* ctrl) {
@@ -1121,7 +1137,13 @@ __global__ __launch_bounds__(kRankTile) void tree_rank_kernel(int n, const int32
     if (!ctrl[C_ORDERED]) return;
     const int total = ctrl[C_TILES];
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
-        const int g = owner[tile];
+        int lo = 0, hi = n - 1;  // the group owning the tile: last g with tstart[g] <= tile
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tstart[mid] <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        const int g = lo;
         const int m = gcount[g];
         const int nt = (m + kRankTile - 1) / kRankTile;
         const int local = tile - tstart[g];
@@ -1400,20 +1422,19 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
     APPD_LAUNCH("tree_link_kernel", s,
         tree_link_kernel<<<nb, 256, 0, s>>>(n, w.keyup, w.link, w.gcount, w.ctrl));
     APPD_CHK();
-    // the packed (size, arrivals) words go to lb and the rank-tile owners to
-    // best (2n ints; at most (n/256 + 1)^2 <= 2n tiles): both are free by now
+    // the packed (size, arrivals) words go to lb, free by now
     const int nsb = (n + kScanBlock - 1) / kScanBlock;
     APPD_LAUNCH("tree_sizes_scan_kernel", s,
         tree_sizes_scan_kernel<<<nsb + nb, kScanThreads, 0, s>>>(n, nsb, w.link, w.lb, w.gcount,
-            w.gstart, w.gfill, w.tstart, (int32_t*)w.best, w.ctrl));
+            w.gstart, w.gfill, w.tstart, w.ctrl));
     APPD_CHK();
     APPD_LAUNCH("tree_group_kernel", s,
-        tree_group_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.gfill, w.grouped, w.rank,
-            w.ctrl));
+        tree_group_kernel<<<(n + kGroupThreads - 1) / kGroupThreads, kGroupThreads, 0, s>>>(n,
+            w.link, w.gstart, w.gfill, w.grouped, w.rank, w.ctrl));
     APPD_CHK();
     APPD_LAUNCH("tree_rank_kernel", s,
-        tree_rank_kernel<<<1024, kRankTile, 0, s>>>(n, w.gcount, w.gstart, w.tstart,
-            (const int32_t*)w.best, w.grouped, w.keyup, w.rank, w.ctrl));
+        tree_rank_kernel<<<1024, kRankTile, 0, s>>>(n, w.gcount, w.gstart, w.tstart, w.grouped,
+            w.keyup, w.rank, w.ctrl));
     APPD_CHK();
     APPD_LAUNCH("tree_place_kernel", s,
         tree_place_kernel<<<nb, 256, 0, s>>>(n, w.link, w.gstart, w.rank, w.lb, w.sorted_size,

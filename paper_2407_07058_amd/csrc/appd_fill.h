@@ -285,8 +285,13 @@ __device__ __forceinline__ void fill_rows_block(const int32_t* __restrict__ pos,
 // values) are coded between the gaps by their rank among the sorted gaps
 // (a two-step ballot search), with per-wave decode entries at CB + 2 * wave
 // (left) and CB + 2 * wave + 1 (right).  A wave locates its next row and
-// issues that row's ek loads before it fills the current one.  s_R: this wave's row buffer of CB codes; s_dM / s_dI: CB + 2 *
-// nwaves entries.
+// issues that row's ek loads before it fills the current one.  M and idx are
+// written with non-temporal stores: n^2 outputs are far larger than the
+// last-level cache, and lines left dirty there would be written back during
+// whatever runs next (the following pass over W).  s_R: this wave's row
+// buffer of CB codes; s_dM / s_dI: CB + 2 * nwaves entries.
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef int i4v __attribute__((ext_vector_type(4)));
 template <int CB, bool WIDEST, bool VEC>
 __device__ __forceinline__ void fill_rows_block_coded(
     const int32_t* __restrict__ pos, const uint64_t* __restrict__ ek, int n, int j0, int cnt,
@@ -468,14 +473,16 @@ __device__ __forceinline__ void fill_rows_block_coded(
                 const uint32_t c1 = s_R[(sl >> 16) & 0xffff] & kCodeMask;
                 const uint32_t c2 = s_R[(sl >> 32) & 0xffff] & kCodeMask;
                 const uint32_t c3 = s_R[sl >> 48] & kCodeMask;
-                *(float4*)(mrow + c) = make_float4(s_dM[c0], s_dM[c1], s_dM[c2], s_dM[c3]);
-                *(int4*)(irow + c) = make_int4(s_dI[c0], s_dI[c1], s_dI[c2], s_dI[c3]);
+                const f4v mv = {s_dM[c0], s_dM[c1], s_dM[c2], s_dM[c3]};
+                const i4v iv = {s_dI[c0], s_dI[c1], s_dI[c2], s_dI[c3]};
+                __builtin_nontemporal_store(mv, (f4v*)(mrow + c));
+                __builtin_nontemporal_store(iv, (i4v*)(irow + c));
             }
         } else {
             for (int c = lane; c < cnt; c += kWave) {
                 const uint32_t cd = s_R[s_slot[c]] & kCodeMask;
-                mrow[c] = s_dM[cd];
-                irow[c] = s_dI[cd];
+                __builtin_nontemporal_store(s_dM[cd], mrow + c);
+                __builtin_nontemporal_store(s_dI[cd], irow + c);
             }
         }
         wave_lds_sync();

@@ -66,6 +66,10 @@ enum appd_mode {
 #define APPD_TREE_PRIM 0x10    /* Prim's algorithm in one workgroup (Section 3) */
 #define APPD_TREE_BORUVKA 0x20 /* Boruvka rounds over per-row candidate lists, then
                                   Prim's attachment order rebuilt from the tree */
+/* Testing aid, with APPD_TREE_BORUVKA or APPD_TREE_AUTO: the Boruvka tree gets
+ * a single pass over W, so that a graph it cannot finish from that pass's
+ * candidate lists goes to the sequential Prim fallback (same results). */
+#define APPD_TREE_ONE_PASS 0x40
 
 const char* appd_error_string(int code);
 int appd_get_last_error(void);

@@ -23,7 +23,9 @@ LIB_PATH = os.path.join(_PKG, "libappd.so")
 MINIMAX = 0
 WIDEST = 1
 MAX_N = 46340
-TREE_FLAGS = {"auto": 0x00, "prim": 0x10, "boruvka": 0x20}
+TREE_FLAGS = {"auto": 0x00, "prim": 0x10, "boruvka": 0x20,
+              # testing aid: one pass over W, then the Prim fallback if needed
+              "boruvka_one_pass": 0x60}
 
 APPD_OK = 0
 APPD_EINVAL = -1

@@ -140,7 +140,7 @@ constexpr int kParallelTreeMinN = 512;
 int parallel_tree_min_n() { return kParallelTreeMinN; }
 
 bool valid_mode(int mode) {
-    if (mode & ~0x31) return false;
+    if (mode & ~(0x31 | APPD_TREE_ONE_PASS)) return false;
     return (mode & 0x30) != 0x30;
 }
 

@@ -30,6 +30,7 @@
 // of the siblings with smaller keys.
 #include "appd_device.h"
 #include "appd_internal.h"
+#include "appd.h"
 #include "appd_prim.h"
 
 namespace appd {
@@ -891,14 +892,10 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
 
 // Edge key to the parent, link initialised to the parent.
 template <bool WIDEST>
-__global__ __launch_bounds__(256) void tree_keyup_kernel(const float* __restrict__ W, int n,
-                                                        const int32_t* par, uint64_t* keyup,
-                                                        int32_t* link, int32_t* size,
-                                                        int32_t* gcount, int32_t* arrived,
-                                                        uint64_t* sa, const int32_t* ctrl) {
-    if (!ctrl[C_ORDERED]) return;
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
+__device__ __forceinline__ void keyup_vertex(const float* __restrict__ W, int n, const int32_t* par,
+                                             uint64_t* keyup, int32_t* link, int32_t* size,
+                                             int32_t* gcount, int32_t* arrived, uint64_t* sa,
+                                             int v) {
     const int p = par[v];
     uint64_t k = 0;
     if (p >= 0) k = make_key((WIDEST ? -1.0f : 1.0f) * W[(size_t)v * n + p], flat_idx(v, p, n));
@@ -908,6 +905,18 @@ __global__ __launch_bounds__(256) void tree_keyup_kernel(const float* __restrict
     gcount[v] = 0;
     arrived[v] = 0;
     if (sa) sa[v] = 1ull << 32;  // packed (size, arrivals): size 1, none arrived
+}
+
+template <bool WIDEST>
+__global__ __launch_bounds__(256) void tree_keyup_kernel(const float* __restrict__ W, int n,
+                                                        const int32_t* par, uint64_t* keyup,
+                                                        int32_t* link, int32_t* size,
+                                                        int32_t* gcount, int32_t* arrived,
+                                                        uint64_t* sa, const int32_t* ctrl) {
+    if (!ctrl[C_ORDERED]) return;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    keyup_vertex<WIDEST>(W, n, par, keyup, link, size, gcount, arrived, sa, v);
 }
 
 // arr[target] += 1 for every active lane.  Lanes aiming at vertex 0 (the
@@ -1274,15 +1283,27 @@ __global__ __launch_bounds__(256) void tree_pos_kernel(int n, const int32_t* lin
     out.parent[v] = par[v];
 }
 
-// Sequential Prim, run only when the rounds could not finish the tree.
+// The two ends of the rounds in one launch (they exclude each other): block 0
+// runs sequential Prim (the fallback) if the rounds did not finish the tree,
+// blocks 1.. compute the parent-edge keys of the order phase if they did.
 template <int CH, bool WIDEST>
-__global__ __launch_bounds__(1024) void tree_fallback_kernel(const float* __restrict__ W, int n,
-                                                            PrimOut out, int32_t* ctrl) {
+__global__ __launch_bounds__(1024) void tree_finish_kernel(const float* __restrict__ W, int n,
+                                                          PrimOut out, const int32_t* par,
+                                                          uint64_t* keyup, int32_t* link,
+                                                          int32_t* size, int32_t* gcount,
+                                                          int32_t* arrived, uint64_t* sa,
+                                                          int32_t* ctrl) {
     __shared__ uint64_t red_key[2 * 16];
     __shared__ int32_t red_v[2 * 16];
-    if (ctrl[C_DONE]) return;
-    if (threadIdx.x == 0) ctrl[C_FALLBACK] = 1;
-    prim_run<1024, CH, WIDEST>(W, n, out, red_key, red_v);
+    if (blockIdx.x == 0) {
+        if (ctrl[C_DONE]) return;
+        if (threadIdx.x == 0) ctrl[C_FALLBACK] = 1;
+        prim_run<1024, CH, WIDEST>(W, n, out, red_key, red_v);
+        return;
+    }
+    if (!ctrl[C_ORDERED]) return;
+    const int v = (blockIdx.x - 1) * 1024 + threadIdx.x;
+    if (v < n) keyup_vertex<WIDEST>(W, n, par, keyup, link, size, gcount, arrived, sa, v);
 }
 
 // ---------------------------------------------------------------- host side
@@ -1329,24 +1350,26 @@ static TreeWs carve_tree(void* ws, int n) {
 size_t tree_workspace_bytes(int n) { return carve_tree(nullptr, n).bytes; }
 
 template <bool WIDEST>
-static hipError_t launch_fallback(const float* W, int n, PrimOut out, int32_t* ctrl,
-                                  hipStream_t s) {
+static hipError_t launch_finish(const float* W, int n, PrimOut out, const TreeWs& w,
+                                hipStream_t s) {
     const int ch = (n + 1023) / 1024;
-#define APPD_FB(C)                                                                   \
-    if (ch <= C) {                                                                   \
-        APPD_LAUNCH("tree_fallback_kernel", s,                                       \
-                    tree_fallback_kernel<C, WIDEST><<<1, 1024, 0, s>>>(W, n, out, ctrl)); \
-        return hipGetLastError();                                                    \
+    const int blocks = 1 + (n + 1023) / 1024;
+#define APPD_FIN(C)                                                                        \
+    if (ch <= C) {                                                                         \
+        APPD_LAUNCH("tree_finish_kernel", s,                                               \
+                    tree_finish_kernel<C, WIDEST><<<blocks, 1024, 0, s>>>(W, n, out, w.par, \
+                        w.keyup, w.link, w.size, w.gcount, w.hook, w.lb, w.ctrl));         \
+        return hipGetLastError();                                                          \
     }
-    APPD_FB(1)
-    APPD_FB(2)
-    APPD_FB(4)
-    APPD_FB(8)
-    APPD_FB(16)
-    APPD_FB(24)
-    APPD_FB(32)
-    APPD_FB(46)
-#undef APPD_FB
+    APPD_FIN(1)
+    APPD_FIN(2)
+    APPD_FIN(4)
+    APPD_FIN(8)
+    APPD_FIN(16)
+    APPD_FIN(24)
+    APPD_FIN(32)
+    APPD_FIN(46)
+#undef APPD_FIN
     return hipErrorInvalidValue;
 }
 
@@ -1379,7 +1402,7 @@ static void launch_refresh(const float* W, int n, const TreeWs& w, hipStream_t s
 }
 
 template <bool WIDEST>
-static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* tws,
+static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* tws, int passes,
                                       hipStream_t s) {
     TreeWs w = carve_tree(tws, n);
     const int nb = (n + 255) / 256;
@@ -1399,7 +1422,7 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
     }
     RoundArgs ra{W,      n,    w.comp, w.best, w.lb, w.lptr, (const uint32_t*)w.lists,
                  w.hook, w.hx, w.hy,   w.par,  w.ctrl, w.cmpart, cm};
-    for (int p = 0; p < kPasses; ++p) {
+    for (int p = 0; p < passes; ++p) {
         if (p == 0)
             launch_first_pass<WIDEST>(W, n, w, s);
         else  // candidate lists, or the component table once few are left
@@ -1413,12 +1436,8 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
                 tree_rounds_kernel<false, WIDEST><<<1, kRoundThreads, round_lds, s>>>(ra));
         APPD_CHK();
     }
-    e = launch_fallback<WIDEST>(W, n, out, w.ctrl, s);
+    e = launch_finish<WIDEST>(W, n, out, w, s);
     if (e != hipSuccess) return e;
-    APPD_LAUNCH("tree_keyup_kernel", s,
-        tree_keyup_kernel<WIDEST><<<nb, 256, 0, s>>>(W, n, w.par, w.keyup, w.link, w.size, w.gcount,
-            w.hook, w.lb, w.ctrl));
-    APPD_CHK();
     APPD_LAUNCH("tree_link_kernel", s,
         tree_link_kernel<<<nb, 256, 0, s>>>(n, w.keyup, w.link, w.gcount, w.ctrl));
     APPD_CHK();
@@ -1455,8 +1474,9 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
 
 hipError_t run_tree_parallel(const float* W, int n, int mode, const PrimOut& out, void* tws,
                              hipStream_t s) {
-    return (mode & 1) ? run_tree_parallel_t<true>(W, n, out, tws, s)
-                      : run_tree_parallel_t<false>(W, n, out, tws, s);
+    const int passes = (mode & APPD_TREE_ONE_PASS) ? 1 : kPasses;
+    return (mode & 1) ? run_tree_parallel_t<true>(W, n, out, tws, passes, s)
+                      : run_tree_parallel_t<false>(W, n, out, tws, passes, s);
 }
 
 // ---------------------------------------------------------------- dendrogram

@@ -134,3 +134,33 @@ def test_boruvka_component_table(k, mode):
     assert np.array_equal(M.cpu().numpy().view(np.uint32), Mo.view(np.uint32))
     assert np.array_equal(idx.cpu().numpy(), io)
     assert st["boruvka"] and not st["fallback"] and st["tables"] >= 1, st
+
+
+@pytest.mark.parametrize("mode", [appd.MINIMAX, appd.WIDEST])
+def test_boruvka_prim_fallback(mode):
+    """Clustered points need a component-table pass; limited to one pass over W,
+    the rounds cannot finish and the sequential Prim fallback runs instead.
+    Bit-exact against the oracle either way.  (In widest mode the weights are
+    reflected, c - W, so that the maximum spanning tree has the clusters.)"""
+    say("case prim fallback mode=%d" % mode)
+    rng = np.random.default_rng(77)
+    centres = rng.random((6, 3)) * 100
+    X = centres[rng.integers(0, 6, 1500)] + 0.2 * rng.standard_normal((1500, 3))
+    W = workloads.euclid_w(X)
+    if mode == appd.WIDEST:  # the maximum spanning tree of c - W is the clustered one
+        W = np.float32(W.max() + 1.0) - W
+        np.fill_diagonal(W, 0.0)
+    Wd = torch.from_numpy(W).to(DEV)
+    ws = torch.empty(appd.workspace_bytes(1500), dtype=torch.uint8, device=DEV)
+    M, idx, order, parent = appd.forward(Wd, mode=mode, tree="boruvka_one_pass", workspace=ws,
+                                         return_tree=True)
+    torch.cuda.synchronize()
+    st = appd.tree_stats(1500, ws, mode=mode, tree="boruvka_one_pass")
+    assert st["boruvka"] and st["fallback"] and st["passes"] == 1, st
+    ref = oracle.appd_widest if mode == appd.WIDEST else oracle.appd
+    Mo, io = ref(W)
+    assert np.array_equal(M.cpu().numpy().view(np.uint32), Mo.view(np.uint32))
+    assert np.array_equal(idx.cpu().numpy(), io)
+    oo, po, _, _ = oracle.mst_prim(W, widest=mode == appd.WIDEST)
+    assert np.array_equal(order.cpu().numpy(), oo)
+    assert np.array_equal(parent.cpu().numpy(), po)

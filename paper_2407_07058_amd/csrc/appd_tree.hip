@@ -15,7 +15,10 @@
 // its outgoing edges from below by its K-th entry.  A component whose best exact
 // candidate is below every such bound has found its cheapest outgoing edge,
 // which is a tree edge (cut property), and hooks along it.  When no component can
-// decide, another pass refreshes the lists.  Each hooking component is re-rooted
+// decide, another pass refreshes the lists (entries inside the row's own
+// component skipped), or, once at most kCmat components are left, computes the
+// smallest edge key between every pair of components, from which the rounds
+// finish the tree exactly.  Each hooking component is re-rooted
 // at its endpoint (the parent pointers on the path to its old root are
 // reversed), so the merged tree stays rooted; at the end it is re-rooted at
 // vertex 0.  If the tree is not complete after kPasses passes, the sequential

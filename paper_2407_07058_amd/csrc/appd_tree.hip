@@ -66,6 +66,11 @@ enum { C_DONE = 0, C_NCOMP, C_NEED_PASS, C_FALLBACK, C_ROUNDS, C_ORDERED, C_PASS
 // (C_CMAT = the number of components it saw); the next rounds call then
 // finishes the tree from that exact kCmat x kCmat table.
 constexpr int kCmat = 16;
+// Up to this n a round that leaves at most kCmat components, some of which
+// could not decide (their lists are running dry), hands over to the component
+// table at once: its pass reads 2n^2 bytes, which costs no more than the list
+// rounds it replaces.  Above it the rounds carry on while they can.
+constexpr int kEarlyTableMaxN = 16384;
 constexpr int C_TILES = 32;
 
 // List entries are ord32(w) << 32 | v: within one row the flat index of (u, v)
@@ -782,6 +787,7 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
         __syncthreads();
         const int decided = s_flag[0];
         const int pending = s_flag[3];
+        const int c_before = C;
         __syncthreads();  // every thread has read the counters
         if (t == 0) s_flag[3] = 0;  // ordered before the next round by the barriers below
         if (decided == 0) {
@@ -864,6 +870,10 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
         }
         __syncthreads();
         if (C == 1) break;
+        if (!dmode && C <= kCmat && decided < c_before && n <= kEarlyTableMaxN) {
+            if (t == 0) ctrl[C_NEED_PASS] = 1;
+            break;
+        }
     }
     __syncthreads();
     const bool done = ctrl[C_DONE] != 0;

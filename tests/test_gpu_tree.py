@@ -164,3 +164,29 @@ def test_boruvka_prim_fallback(mode):
     oo, po, _, _ = oracle.mst_prim(W, widest=mode == appd.WIDEST)
     assert np.array_equal(order.cpu().numpy(), oo)
     assert np.array_equal(parent.cpu().numpy(), po)
+
+
+@pytest.mark.parametrize("n,mode", [(2401, appd.MINIMAX), (1999, appd.WIDEST)])
+def test_boruvka_component_table_odd_n(n, mode):
+    """The component-table pass on a size that is not a multiple of 4 (scalar
+    loads) and odd (the middle row has no partner row): bit-exact against the
+    oracle, and the table pass ran.  In widest mode the weights are reflected,
+    c - W, so that the maximum spanning tree has the clusters."""
+    say("case boruvka component table n=%d mode=%d" % (n, mode))
+    rng = np.random.default_rng(n)
+    centres = rng.random((5, 4)) * 100
+    X = centres[rng.integers(0, 5, n)] + 0.3 * rng.standard_normal((n, 4))
+    W = workloads.euclid_w(X)
+    if mode == appd.WIDEST:
+        W = np.float32(W.max() + 1.0) - W
+        np.fill_diagonal(W, 0.0)
+    Wd = torch.from_numpy(W).to(DEV)
+    ws = torch.empty(appd.workspace_bytes(n), dtype=torch.uint8, device=DEV)
+    M, idx = appd.forward(Wd, mode=mode, tree="boruvka", workspace=ws)
+    torch.cuda.synchronize()
+    st = appd.tree_stats(n, ws, mode=mode, tree="boruvka")
+    ref = oracle.appd_widest if mode == appd.WIDEST else oracle.appd
+    Mo, io = ref(W)
+    assert np.array_equal(M.cpu().numpy().view(np.uint32), Mo.view(np.uint32))
+    assert np.array_equal(idx.cpu().numpy(), io)
+    assert st["boruvka"] and not st["fallback"] and st["tables"] >= 1, st

@@ -47,16 +47,21 @@ constexpr int kMaxLdsN = 32768;    // comp + parent as 16-bit values in LDS
 constexpr int kLdsBytes = 150 * 1024;  // dynamic LDS the rounds kernel may take
 constexpr int kTableBytes = 28;        // per-component table entry
 constexpr uint64_t kNone = ~0ull;
-constexpr uint16_t kNoId = 0xffff;  // end of a short list (n < 65535 always)
-// A vertex's list is stored as K/4 groups of 32 bytes: the vertex ids of four
-// consecutive entries (u16, bytes 0-7), their ord32 weights (u32, bytes 8-23),
-// 8 bytes of padding.  Group g of vertex u sits at (g * n + u) * 32 bytes, so
-// the waves of the rounds kernel, whose lanes hold consecutive vertices, read
-// contiguous memory.  The edge key of an entry is ord32 << 32 | flat(u, id).
-constexpr int kGroupWords = 8;
-#ifndef APPD_WALK_GROUPS
-#define APPD_WALK_GROUPS 2
-#endif
+// A vertex's list is stored as K/4 groups of four consecutive entries, in two
+// planes: the vertex ids of group g of vertex u (4 x u16) at word
+// (g * n + u) * 2, their ord32 weights (4 x u32) at word K/2 * n + (g * n + u) * 4.
+// A wave of the rounds kernel, whose lanes hold consecutive vertices, then
+// reads 512 and 1024 contiguous bytes for one group of 64 vertices (and touches
+// 12 cache lines, not the 32 of an interleaved 32-byte record).  The edge key of
+// an entry is ord32 << 32 | flat(u, id).  The planes take 96 of the 128 bytes
+// per vertex the workspace reserves for the lists.  A list shorter than K
+// (only when n <= K: a refresh pass runs with more than K components, so every
+// row then has K entries outside its own) is padded with the vertex itself,
+// which every walk sees as internal.
+__device__ __forceinline__ size_t grp_ids(int n, int g, int u) { return ((size_t)g * n + u) * 2; }
+__device__ __forceinline__ size_t grp_ords(int n, int g, int u) {
+    return (size_t)(kK / 2) * n + ((size_t)g * n + u) * 4;
+}
 
 // control block (int32 words); word 32 holds the number of rank tiles
 enum { C_DONE = 0, C_NCOMP, C_NEED_PASS, C_FALLBACK, C_ROUNDS, C_ORDERED, C_PASSES, C_CMAT,
@@ -201,10 +206,10 @@ __device__ __forceinline__ void pass_row(const float* __restrict__ W, int n,
             }
         }
     }
-    if (lane < kK) {  // group lane/4, slot lane%4 (layout: see kGroupWords)
-        uint32_t* g = groups + ((size_t)(lane >> 2) * n + u) * kGroupWords;
-        ((uint16_t*)g)[lane & 3] = mine == kNone ? kNoId : (uint16_t)(uint32_t)mine;
-        g[2 + (lane & 3)] = (uint32_t)(mine >> 32);
+    if (lane < kK) {  // group lane/4, slot lane%4 (layout: see grp_ids)
+        ((uint16_t*)(groups + grp_ids(n, lane >> 2, u)))[lane & 3] =
+            (uint16_t)(mine == kNone ? (uint32_t)u : (uint32_t)mine);
+        groups[grp_ords(n, lane >> 2, u) + (lane & 3)] = (uint32_t)(mine >> 32);
     }
     if (lane == 0) lptr[u] = 0;
 }
@@ -367,7 +372,7 @@ struct RoundArgs {
     uint64_t* best;
     uint64_t* lb;
     int32_t* lptr;
-    const uint32_t* groups;  // candidate lists, K/4 groups of kGroupWords words per vertex
+    const uint32_t* groups;  // candidate lists (layout: see grp_ids)
     int32_t* hook;
     int32_t* hx;  // hooking endpoint inside the component
     int32_t* hy;  // endpoint outside
@@ -424,6 +429,11 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
     const int lane = t & (kWave - 1);
     int32_t* ctrl = a.ctrl;
     if (ctrl[C_ORDERED] || ctrl[C_FALLBACK]) return;
+    // control words read once; this workgroup alone updates them until it
+    // ends, so they live in registers (uniform) and are written at the end
+    bool done = ctrl[C_DONE] != 0;
+    int rounds = ctrl[C_ROUNDS];
+    bool need_pass = false;
     // LDS layout: [per-component tables: best, lb (u64) | hook, hx, hy (i32)]
     //             [per-vertex: component, parent (u16)]
     uint64_t* t_best = s_dyn;
@@ -479,7 +489,7 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
         else a.hy[d] = y;
     };
     // the rooted forest built so far (first call: every vertex its own root)
-    const bool first = ctrl[C_ROUNDS] == 0;
+    const bool first = rounds == 0;
     // after a component-table pass: c0 components, table entry (a, b) names the
     // smallest edge between them; s_cmap follows each one's current number
     __shared__ int s_cmap[kCmat];
@@ -517,7 +527,7 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
         if (t < kCmat * kCmat) s_cm[t] = sym;
         __syncthreads();
     }
-    if (LDS && first && !ctrl[C_DONE]) {
+    if (LDS && first && !done) {
         // Round 1, all in LDS.  Every vertex is its own component and its list's
         // first entry is its cheapest edge, so it hooks along it; the only
         // cycles are pairs that chose the same edge, whose smaller vertex stays
@@ -528,20 +538,35 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
 #pragma unroll
             for (int i = 0; i < kV; ++i) {
                 const int u = base + i * kRoundThreads + t;
-                e[i] = u < n ? *(const uint16_t*)(a.groups + (size_t)u * kGroupWords) : kNoId;
+                e[i] = u < n ? *(const uint16_t*)(a.groups + grp_ids(n, 0, u)) : 0;
             }
 #pragma unroll
             for (int i = 0; i < kV; ++i) {
                 const int u = base + i * kRoundThreads + t;
-                if (u < n) v_par[u] = e[i] == kNoId ? (uint16_t)u : e[i];
+                if (u < n) v_par[u] = e[i];  // an empty list holds u itself
             }
         }
         __syncthreads();
-        // roots: vertices hooked to themselves, and the smaller end of a pair
+        // roots: vertices hooked to themselves, and the smaller end of a pair.
+        // The per-vertex loops below go kB vertices at a time, every LDS read
+        // of a batch issued before the first is used (and before any store).
+        constexpr int kB = 8;
         uint32_t rootbits = 0;  // bit i: vertex t + i * kRoundThreads (n <= 32 * 1024)
-        for (int i = 0, u = t; u < n; ++i, u += kRoundThreads) {
-            const int h = v_par[u];
-            if (h == u || (v_par[h] == u && u < h)) rootbits |= 1u << i;
+        for (int i0 = 0; i0 * kRoundThreads < n; i0 += kB) {
+            int h[kB], hh[kB];
+#pragma unroll
+            for (int j = 0; j < kB; ++j) {
+                const int u = (i0 + j) * kRoundThreads + t;
+                h[j] = u < n ? v_par[u] : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < kB; ++j) hh[j] = v_par[h[j]];
+#pragma unroll
+            for (int j = 0; j < kB; ++j) {
+                const int u = (i0 + j) * kRoundThreads + t;
+                const bool r = u < n && (h[j] == u || (hh[j] == u && u < h[j]));
+                rootbits |= r ? 1u << (i0 + j) : 0u;
+            }
         }
         __syncthreads();
         for (int i = 0, u = t; u < n; ++i, u += kRoundThreads) {
@@ -555,12 +580,22 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
             if (t == 0) s_flag[1] = 0;
             __syncthreads();
             bool ch = false;
-            for (int u = t; u < n; u += kRoundThreads) {
-                const int c = v_comp[u];
-                const int cc = v_comp[c];
-                if (cc != c) {
-                    v_comp[u] = (uint16_t)cc;
-                    ch = true;
+            for (int u0 = t; u0 < n; u0 += kB * kRoundThreads) {
+                int c[kB], cc[kB];
+#pragma unroll
+                for (int j = 0; j < kB; ++j) {
+                    const int u = u0 + j * kRoundThreads;
+                    c[j] = u < n ? v_comp[u] : 0;
+                }
+#pragma unroll
+                for (int j = 0; j < kB; ++j) cc[j] = v_comp[c[j]];
+#pragma unroll
+                for (int j = 0; j < kB; ++j) {
+                    const int u = u0 + j * kRoundThreads;
+                    if (u < n && cc[j] != c[j]) {
+                        v_comp[u] = (uint16_t)cc[j];
+                        ch = true;
+                    }
                 }
             }
             if (ch) s_flag[1] = 1;
@@ -586,18 +621,30 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
         if (t == nw - 1) s_flag[2] = pre + __popcll(bits[t]);
         __syncthreads();
         C = s_flag[2];
-        for (int u = t; u < n; u += kRoundThreads) {
-            const int r = v_comp[u];
-            const int w = r / kWave;
-            v_comp[u] = (uint16_t)(wpre[w] + __popcll(bits[w] & ((1ull << (r & (kWave - 1))) - 1)));
+        for (int u0 = t; u0 < n; u0 += kB * kRoundThreads) {
+            int r[kB], pre_w[kB];
+            uint64_t bw[kB];
+#pragma unroll
+            for (int j = 0; j < kB; ++j) {
+                const int u = u0 + j * kRoundThreads;
+                r[j] = u < n ? v_comp[u] : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < kB; ++j) {
+                pre_w[j] = wpre[r[j] / kWave];
+                bw[j] = bits[r[j] / kWave];
+            }
+#pragma unroll
+            for (int j = 0; j < kB; ++j) {
+                const int u = u0 + j * kRoundThreads;
+                const uint64_t below = (1ull << (r[j] & (kWave - 1))) - 1;
+                if (u < n) v_comp[u] = (uint16_t)(pre_w[j] + __popcll(bw[j] & below));
+            }
         }
         __syncthreads();
         small = C <= cm;
-        if (t == 0) {
-            ctrl[C_ROUNDS] = 1;
-            ctrl[C_NCOMP] = C;
-            if (C == 1) ctrl[C_DONE] = 1;
-        }
+        rounds = 1;
+        done = C == 1;
         for (int d = t; d < C; d += kRoundThreads) {
             if (small) t_best[d] = t_lb[d] = kNone;
             else a.best[d] = a.lb[d] = kNone;
@@ -617,26 +664,24 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
     __syncthreads();
 
     // 1. cheapest outgoing candidate (or lower bound) of every vertex.  Each
-    //    round a vertex reads the 32-byte group of its list that holds its list
-    //    pointer (ids and weights of four entries) and checks the rest of the
-    //    group, endpoint components from LDS.  The first entry leaving its
-    //    component is its exact cheapest outgoing edge.  If the rest of the
-    //    group is internal, every outgoing edge of the vertex is larger than
-    //    the group's last entry, which becomes a lower bound, and the pointer
-    //    moves to the next group (the vertex is "pending": its walk continues
-    //    next round); an exhausted list bounds by its entry K-1.  A round in
-    //    which no component decides but some vertex is pending is followed by
-    //    another round on the same lists.  A wave whose vertices share one
-    //    component sends one atomic per minimum.
-    constexpr int kW = 8;  // vertices per thread
-    constexpr int kWalkGroups = APPD_WALK_GROUPS;  // list groups a vertex may read per round
+    //    round a vertex reads a window of eight list entries: the group of four
+    //    that holds its list pointer and the group after it (ids and weights,
+    //    two independent loads each), and checks the entries from the pointer
+    //    on, endpoint components from LDS.  The first entry leaving its
+    //    component is its exact cheapest outgoing edge.  If every entry checked
+    //    is internal, every outgoing edge of the vertex is larger than the
+    //    window's last entry, which becomes a lower bound, and the pointer moves
+    //    past the window (the vertex is "pending": its walk continues next
+    //    round); an exhausted list bounds by its entry K-1.  A round in which no
+    //    component decides but some vertex is pending is followed by another
+    //    round on the same lists.  A wave whose vertices share one component
+    //    sends one atomic per minimum.
+    constexpr int kW = 4;  // vertices per thread
     constexpr int kStride = kW * kRoundThreads;
-    constexpr int GW = kGroupWords;
-    for (int guard = 0; guard < 128 && !ctrl[C_DONE]; ++guard) {
-        if (t == 0) {
-            s_flag[0] = 0;  // components that decided this round
-            ctrl[C_ROUNDS] += 1;
-        }
+    constexpr int kLastGroup = kK / 4 - 1;
+    for (int guard = 0; guard < 128 && !done; ++guard) {
+        if (t == 0) s_flag[0] = 0;  // components that decided this round
+        ++rounds;
         if (dmode) {
             // exact: every component's cheapest edge to any other one
             for (int e = t; e < c0 * c0; e += kRoundThreads) {
@@ -648,8 +693,8 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
         }
         for (int base = 0; !dmode && base < n; base += kStride) {
             int pp[kW];
-            uint4 gr[kW];  // ids (x, y) and ords of entries 0, 1 (z, w) of the group
-            uint2 go[kW];  // ords of entries 2, 3
+            uint2 gi[kW][2];  // ids of the window's two groups (u16 pairs)
+            uint4 go[kW][2];  // their ord32 weights
 #pragma unroll
             for (int i = 0; i < kW; ++i) {
                 const int u = base + i * kRoundThreads + t;
@@ -658,84 +703,75 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
 #pragma unroll
             for (int i = 0; i < kW; ++i) {
                 const int u = base + i * kRoundThreads + t;
-                if (u < n) {  // an exhausted list needs only its last group (the bound)
-                    const int g = pp[i] < kK ? (pp[i] >> 2) : kK / 4 - 1;
-                    const uint32_t* G = a.groups + ((size_t)g * n + u) * GW;
-                    gr[i] = *(const uint4*)G;
-                    go[i] = *(const uint2*)(G + 4);
+                // an exhausted list reads its last group (for the bound); the
+                // window's second group past the end repeats the last one
+                const int g0 = min(pp[i] >> 2, kLastGroup);
+                const int g1 = min(g0 + 1, kLastGroup);
+                gi[i][0] = gi[i][1] = make_uint2(0u, 0u);
+                go[i][0] = go[i][1] = make_uint4(0u, 0u, 0u, 0u);
+                if (u < n) {
+                    gi[i][0] = *(const uint2*)(a.groups + grp_ids(n, g0, u));
+                    go[i][0] = *(const uint4*)(a.groups + grp_ords(n, g0, u));
+                    gi[i][1] = *(const uint2*)(a.groups + grp_ids(n, g1, u));
+                    go[i][1] = *(const uint4*)(a.groups + grp_ords(n, g1, u));
                 }
             }
             int npend = 0;
-            int cuv[kW];
             uint64_t key[kW];
-            uint32_t walk = 0, isb = 0, pendm = 0, moved = 0;  // bit i: vertex i
+            int cuv[kW];
+            uint32_t isb = 0, pendm = 0, moved = 0;  // bit i: vertex i
 #pragma unroll
             for (int i = 0; i < kW; ++i) {
                 const int u = base + i * kRoundThreads + t;
-                cuv[i] = u < n ? getc(u) : -1;
-                key[i] = kNone;
-                if (u < n) walk |= 1u << i;
-            }
-            // lists shorter than K (end marked by kNoId) exist only when n <= K
-            const bool shortlists = n <= kK;
-            for (int step = 0; step < kWalkGroups; ++step) {
-                uint32_t next = 0;
+                const bool act = u < n;
+                const int cu = getc(act ? u : 0);
+                cuv[i] = cu;
+                // window entry w is list entry 4 * g0 + w; its id is half w & 1
+                // of word w >> 1.  Lookups unconditional (ids are always < n),
+                // combined bitwise: no branch separates the LDS reads.
+                uint32_t idw[4] = {gi[i][0].x, gi[i][0].y, gi[i][1].x, gi[i][1].y};
+                uint32_t ow[8] = {go[i][0].x, go[i][0].y, go[i][0].z, go[i][0].w,
+                                  go[i][1].x, go[i][1].y, go[i][1].z, go[i][1].w};
+                // opaque register values: the selects below must stay selects
+                // (folded into an index they would put the window in scratch)
 #pragma unroll
-                for (int i = 0; i < kW; ++i) {
-                    const int u = base + i * kRoundThreads + t;
-                    const uint32_t id4[4] = {gr[i].x & 0xffffu, gr[i].x >> 16, gr[i].y & 0xffffu,
-                                             gr[i].y >> 16};
-                    const uint32_t od4[4] = {gr[i].z, gr[i].w, go[i].x, go[i].y};
-                    // bit r: entry q+r leaves the vertex's component (components
-                    // looked up unconditionally: no branch between the LDS reads)
-                    uint32_t ext = 0, nil = 0;
+                for (int w = 0; w < 4; ++w) asm("" : "+v"(idw[w]));
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const bool ok = id4[r] < (uint32_t)n;
-                        const int c = getc(ok ? (int)id4[r] : 0);
-                        ext |= (ok && c != cuv[i]) ? 1u << r : 0u;
-                        nil |= ok ? 0u : 1u << r;
-                    }
-                    const bool w = (walk >> i) & 1u;
-                    const int p = pp[i];
-                    const int q = p & ~3;
-                    // entries at or after the pointer; an exhausted list (p = K,
-                    // last group loaded) only contributes its entry K-1 as a bound
-                    const uint32_t live = p >= kK ? 0u : (0xfu << (p - q)) & 0xfu;
-                    const uint32_t stop = live & (ext | (shortlists ? nil : 0u));
-                    const int first = stop ? __builtin_ctz(stop) : 3;
-                    uint32_t v = id4[0], o = od4[0];
+                for (int w = 0; w < 8; ++w) asm("" : "+v"(ow[w]));
+                uint32_t ext = 0;
 #pragma unroll
-                    for (int r = 1; r < 4; ++r) {
-                        v = first == r ? id4[r] : v;
-                        o = first == r ? od4[r] : o;
-                    }
-                    const bool shortl = shortlists && ((stop & nil) >> first & 1u);
-                    const bool found = stop && !shortl;
-                    const bool bound = !stop && v < (uint32_t)n;  // group internal: entry q+3 bounds
-                    const int np = p >= kK ? kK : (found ? q + first : (shortl ? kK : q + 4));
-                    if (w) {
-                        walk &= ~(1u << i);
-                        key[i] = (found || bound) ? (((uint64_t)o << 32) | flat_idx(u, v, n)) : kNone;
-                        isb = bound ? (isb | (1u << i)) : (isb & ~(1u << i));
-                        if (np != p) moved |= 1u << i;
-                        pp[i] = np;
-                        if (!found && !shortl && np < kK) {
-                            if (step + 1 < kWalkGroups) next |= 1u << i;
-                            else pendm |= 1u << i;
-                        }
-                    }
+                for (int w = 0; w < 8; ++w) {
+                    const uint32_t id = (w & 1) ? idw[w >> 1] >> 16 : idw[w >> 1] & 0xffffu;
+                    ext |= (uint32_t)(getc((int)id) != cu) << w;
                 }
-                if (!next) break;
-#pragma unroll
-                for (int i = 0; i < kW; ++i) {
-                    if (!((next >> i) & 1u)) continue;
-                    const int u = base + i * kRoundThreads + t;
-                    const uint32_t* G = a.groups + ((size_t)(pp[i] >> 2) * n + u) * GW;
-                    gr[i] = *(const uint4*)G;
-                    go[i] = *(const uint2*)(G + 4);
-                }
-                walk = next;
+                const int p = pp[i];
+                const int g0 = min(p >> 2, kLastGroup);
+                // entries at or after the pointer and inside the list (p = K:
+                // none; the bound is then the entry K-1, window entry 3)
+                const uint32_t inlist = g0 == kLastGroup ? 0x0fu : 0xffu;
+                const uint32_t live = (0xffu << (p - 4 * g0)) & inlist;
+                const uint32_t stop = live & ext;
+                const int last = g0 == kLastGroup ? 3 : 7;
+                const int first = stop ? __builtin_ctz(stop) : last;
+                // select entry `first` by its three bits
+                const bool b0 = first & 1, b1 = first & 2, b2 = first & 4;
+                const uint32_t wlo = b1 ? idw[1] : idw[0], whi = b1 ? idw[3] : idw[2];
+                const uint32_t word = b2 ? whi : wlo;
+                const uint32_t v = b0 ? word >> 16 : word & 0xffffu;
+                const uint32_t o01 = b0 ? ow[1] : ow[0], o23 = b0 ? ow[3] : ow[2];
+                const uint32_t o45 = b0 ? ow[5] : ow[4], o67 = b0 ? ow[7] : ow[6];
+                const uint32_t o = b2 ? (b1 ? o67 : o45) : (b1 ? o23 : o01);
+                const bool found = act && stop != 0;
+                // padding (the vertex itself) bounds nothing: the list held
+                // every outgoing edge of the vertex
+                const bool bound = act && !stop && v != (uint32_t)u;
+                const int np = stop ? 4 * g0 + first : min(4 * g0 + 8, kK);
+                key[i] = (found || bound) ? (((uint64_t)o << 32) | flat_idx(u, v, n)) : kNone;
+                const uint32_t bit = 1u << i;
+                isb |= bound ? bit : 0u;
+                moved |= (act && np != p) ? bit : 0u;
+                pendm |= (act && !stop && np < kK) ? bit : 0u;
+                pp[i] = np;
             }
 #pragma unroll
             for (int i = 0; i < kW; ++i) {
@@ -746,19 +782,19 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
                 const uint64_t kc = isbi ? kNone : key[i];
                 const uint64_t kb = isbi ? key[i] : kNone;
                 const bool pend = (pendm >> i) & 1u;
-                if (act && ((moved >> i) & 1u)) a.lptr[u] = pp[i];
+                if ((moved >> i) & 1u) a.lptr[u] = pp[i];
                 npend += __popcll(__ballot(pend));
-                const int c0 = __builtin_amdgcn_readfirstlane(cu);
-                const uint64_t same = __ballot(act && cu == c0);
+                const int cw = __builtin_amdgcn_readfirstlane(cu);
+                const uint64_t same = __ballot(act && cu == cw);
                 const uint64_t acts = __ballot(act);
                 if (same == acts) {
                     if (__ballot(kc != kNone)) {
                         const uint64_t mc = wave_min_u64(kc);
-                        if (lane == 0) min_best(c0, mc);
+                        if (lane == 0) min_best(cw, mc);
                     }
                     if (__ballot(kb != kNone)) {
                         const uint64_t mb = wave_min_u64(kb);
-                        if (lane == 0) min_lb(c0, mb);
+                        if (lane == 0) min_lb(cw, mb);
                     }
                 } else if (act) {
                     if (kc != kNone) min_best(cu, kc);
@@ -802,7 +838,7 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
                 __syncthreads();
                 continue;
             }
-            if (t == 0) ctrl[C_NEED_PASS] = 1;
+            need_pass = true;
             break;
         }
         // 3. a mutual pair chose the same edge: the smaller id stays the root
@@ -854,7 +890,23 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
         __syncthreads();
         const int Cn = s_flag[2];
         // 6. relabel every vertex; clear the tables for the next round
-        for (int u = t; u < n; u += kRoundThreads) setc(u, gethx(geth(getc(u))));
+        for (int u0 = t; u0 < n; u0 += kW * kRoundThreads) {
+            int c[kW];  // batched as the walk: all reads of a step in flight
+#pragma unroll
+            for (int j = 0; j < kW; ++j) {
+                const int u = u0 + j * kRoundThreads;
+                c[j] = u < n ? getc(u) : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < kW; ++j) c[j] = geth(c[j]);
+#pragma unroll
+            for (int j = 0; j < kW; ++j) c[j] = gethx(c[j]);
+#pragma unroll
+            for (int j = 0; j < kW; ++j) {
+                const int u = u0 + j * kRoundThreads;
+                if (u < n) setc(u, c[j]);
+            }
+        }
         const int cmap_new = (dmode && t < c0) ? gethx(geth(s_cmap[t])) : 0;
         __syncthreads();
         if (dmode && t < c0) s_cmap[t] = cmap_new;
@@ -864,20 +916,22 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
             if (small) t_best[d] = t_lb[d] = kNone;
             else a.best[d] = a.lb[d] = kNone;
         }
-        if (t == 0) {
-            ctrl[C_NCOMP] = C;
-            if (C == 1) ctrl[C_DONE] = 1;
-        }
+        done = C == 1;
         __syncthreads();
         if (C == 1) break;
         if (!dmode && C <= kCmat && decided < c_before && n <= kEarlyTableMaxN) {
-            if (t == 0) ctrl[C_NEED_PASS] = 1;
+            need_pass = true;
             break;
         }
     }
     __syncthreads();
-    const bool done = ctrl[C_DONE] != 0;
-    if (dmode && t == 0) ctrl[C_CMAT] = 0;  // the table is used up
+    if (t == 0) {
+        ctrl[C_ROUNDS] = rounds;
+        ctrl[C_NCOMP] = C;
+        if (done) ctrl[C_DONE] = 1;
+        if (need_pass) ctrl[C_NEED_PASS] = 1;
+        if (dmode) ctrl[C_CMAT] = 0;  // the table is used up
+    }
     if (done && t == 0) {  // re-root at vertex 0
         int cur = 0, prev = -1;
         while (cur >= 0) {

@@ -499,26 +499,37 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
     if (t < kCmat) s_cmap[t] = t;
     if (dmode) {
         // combine the component-table pass's workgroup tables: thread t takes
-        // entry t % 256 of every fourth table, eight loads in flight at a time
-        static_assert(kRoundThreads == 4 * kCmat * kCmat, "four threads per table entry");
-        const int e = t % (kCmat * kCmat), q = t / (kCmat * kCmat);
+        // entries 2p, 2p + 1 (p = t % 128) of every eighth table, one 16-byte
+        // load per table, sixteen in flight at a time
+        constexpr int kPairs = kCmat * kCmat / 2;
+        constexpr int kQ = kRoundThreads / kPairs;
+        constexpr int kInFlight = 16;
+        static_assert(kRoundThreads % kPairs == 0, "whole table pairs per thread group");
+        const int e = 2 * (t % kPairs), q = t / kPairs;
         const int nparts = kCmatBlocks(n);
         if (t < kCmat * kCmat) s_cm[t] = kNone;
-        uint64_t m = kNone;
-        // only entries between the c0 components are ever set
+        uint64_t m0 = kNone, m1 = kNone;
+        // only entries between the c0 components are ever set (e is even, so
+        // e and e + 1 share a row)
         const bool used = e / kCmat < c0 && e % kCmat < c0;
-        for (int g0 = q; used && g0 < nparts; g0 += 4 * 8) {
-            uint64_t v[8];
+        for (int g0 = q; used && g0 < nparts; g0 += kQ * kInFlight) {
+            ulonglong2 v[kInFlight];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int g = g0 + 4 * i;
-                v[i] = a.cmpart[(size_t)(g < nparts ? g : q) * kCmat * kCmat + e];
+            for (int i = 0; i < kInFlight; ++i) {
+                const int g = g0 + kQ * i;  // past the end: table q again
+                v[i] = *(const ulonglong2*)(a.cmpart + (size_t)(g < nparts ? g : q) * kCmat * kCmat + e);
             }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) m = umin64(m, v[i]);
+            for (int i = 0; i < kInFlight; ++i) {
+                m0 = umin64(m0, v[i].x);
+                m1 = umin64(m1, v[i].y);
+            }
         }
         __syncthreads();
-        atomicMin((unsigned long long*)&s_cm[e], (unsigned long long)m);
+        if (used) {
+            atomicMin((unsigned long long*)&s_cm[e], (unsigned long long)m0);
+            atomicMin((unsigned long long*)&s_cm[e + 1], (unsigned long long)m1);
+        }
         __syncthreads();
         // an edge was recorded under its smaller endpoint's component only
         uint64_t sym = kNone;
@@ -679,6 +690,14 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
     constexpr int kW = 4;  // vertices per thread
     constexpr int kStride = kW * kRoundThreads;
     constexpr int kLastGroup = kK / 4 - 1;
+    // list pointers of the next batch of vertices, loaded one batch ahead (and
+    // for the next round's first batch while the round's later steps run)
+    int ppn[kW];
+#pragma unroll
+    for (int i = 0; i < kW; ++i) {
+        const int u = i * kRoundThreads + t;
+        ppn[i] = (!dmode && u < n) ? a.lptr[u] : kK;
+    }
     for (int guard = 0; guard < 128 && !done; ++guard) {
         if (t == 0) s_flag[0] = 0;  // components that decided this round
         ++rounds;
@@ -696,10 +715,7 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
             uint2 gi[kW][2];  // ids of the window's two groups (u16 pairs)
             uint4 go[kW][2];  // their ord32 weights
 #pragma unroll
-            for (int i = 0; i < kW; ++i) {
-                const int u = base + i * kRoundThreads + t;
-                pp[i] = u < n ? a.lptr[u] : kK;
-            }
+            for (int i = 0; i < kW; ++i) pp[i] = ppn[i];
 #pragma unroll
             for (int i = 0; i < kW; ++i) {
                 const int u = base + i * kRoundThreads + t;
@@ -714,6 +730,17 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
                     go[i][0] = *(const uint4*)(a.groups + grp_ords(n, g0, u));
                     gi[i][1] = *(const uint2*)(a.groups + grp_ids(n, g1, u));
                     go[i][1] = *(const uint4*)(a.groups + grp_ords(n, g1, u));
+                }
+            }
+            // the next batch's pointers (this round's next, or the next round's
+            // first, whose stores came earlier in this round); a single batch
+            // keeps its own, updated below
+            const int nb = base + kStride < n ? base + kStride : 0;
+            if (nb != base) {
+#pragma unroll
+                for (int i = 0; i < kW; ++i) {
+                    const int u = nb + i * kRoundThreads + t;
+                    ppn[i] = u < n ? a.lptr[u] : kK;
                 }
             }
             int npend = 0;
@@ -772,6 +799,7 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
                 moved |= (act && np != p) ? bit : 0u;
                 pendm |= (act && !stop && np < kK) ? bit : 0u;
                 pp[i] = np;
+                if (nb == base) ppn[i] = np;
             }
 #pragma unroll
             for (int i = 0; i < kW; ++i) {
@@ -889,9 +917,28 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
         if (t == kRoundThreads - 1) s_flag[2] = id;
         __syncthreads();
         const int Cn = s_flag[2];
-        // 6. relabel every vertex; clear the tables for the next round
+        // 6. every component's new number (the number of its root), kept in
+        //    its hook slot, so that relabelling a vertex takes one lookup
+        constexpr int kRB = 8;  // entries per batch: every read of a step in flight
+        for (int d0 = t; d0 < C; d0 += kRB * kRoundThreads) {
+            int h[kRB];
+#pragma unroll
+            for (int j = 0; j < kRB; ++j) {
+                const int d = d0 + j * kRoundThreads;
+                h[j] = d < C ? geth(d) : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < kRB; ++j) h[j] = gethx(h[j]);
+#pragma unroll
+            for (int j = 0; j < kRB; ++j) {
+                const int d = d0 + j * kRoundThreads;
+                if (d < C) seth(d, h[j]);
+            }
+        }
+        __syncthreads();
+        //    relabel every vertex; clear the tables for the next round
         for (int u0 = t; u0 < n; u0 += kW * kRoundThreads) {
-            int c[kW];  // batched as the walk: all reads of a step in flight
+            int c[kW];
 #pragma unroll
             for (int j = 0; j < kW; ++j) {
                 const int u = u0 + j * kRoundThreads;
@@ -900,14 +947,12 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
 #pragma unroll
             for (int j = 0; j < kW; ++j) c[j] = geth(c[j]);
 #pragma unroll
-            for (int j = 0; j < kW; ++j) c[j] = gethx(c[j]);
-#pragma unroll
             for (int j = 0; j < kW; ++j) {
                 const int u = u0 + j * kRoundThreads;
                 if (u < n) setc(u, c[j]);
             }
         }
-        const int cmap_new = (dmode && t < c0) ? gethx(geth(s_cmap[t])) : 0;
+        const int cmap_new = (dmode && t < c0) ? geth(s_cmap[t]) : 0;
         __syncthreads();
         if (dmode && t < c0) s_cmap[t] = cmap_new;
         C = Cn;

@@ -310,26 +310,39 @@ __global__ __launch_bounds__(kCmatThreads) void tree_refresh_kernel(
         const float* row = W + (size_t)u * (size_t)n;
         const int cu = comp[u] & (kCmat - 1);
         if (VEC) {
+            // a ring of kRing 16-byte loads of W (and of comp) per lane in
+            // flight; the slot just consumed is refilled kRing steps ahead
+            // (clamped to the row's last 16 bytes past the end)
+            constexpr int kRing = 4;
+            constexpr int S = kWave * 4;  // columns per wave step
             const int base = (u + 1) & ~3;  // 16-byte aligned; columns <= u skipped
-            int c0 = base + lane * 4;
-            float4 x = *(const float4*)(row + min(c0, n - 4));
-            int4 c4 = *(const int4*)(comp + min(c0, n - 4));
-            for (; c0 < n; c0 += kWave * 4) {
-                const int c1 = min(c0 + kWave * 4, n - 4);  // prefetch
-                const float4 xn = *(const float4*)(row + c1);
-                const int4 cn = *(const int4*)(comp + c1);
-                if (c0 > u) {
-                    cmat_fold_slot(&col[(c4.x & (kCmat - 1)) * kWave], WIDEST ? -x.x : x.x, c0);
+            const int c0 = base + lane * 4;
+            float4 xb[kRing];
+            int4 cb[kRing];
+#pragma unroll
+            for (int d = 0; d < kRing; ++d) {
+                const int c = min(c0 + d * S, n - 4);
+                xb[d] = *(const float4*)(row + c);
+                cb[d] = *(const int4*)(comp + c);
+            }
+            for (int cc = c0; cc < n; cc += kRing * S) {
+#pragma unroll
+                for (int d = 0; d < kRing; ++d) {
+                    const int c = cc + d * S;
+                    const float4 x = xb[d];
+                    const int4 c4 = cb[d];
+                    const int cn = min(c + kRing * S, n - 4);
+                    xb[d] = *(const float4*)(row + cn);
+                    cb[d] = *(const int4*)(comp + cn);
+                    if (c < n) {  // columns in increasing order, as the ties need
+                        if (c > u) cmat_fold_slot(&col[(c4.x & (kCmat - 1)) * kWave], WIDEST ? -x.x : x.x, c);
+                        if (c + 1 > u)
+                            cmat_fold_slot(&col[(c4.y & (kCmat - 1)) * kWave], WIDEST ? -x.y : x.y, c + 1);
+                        if (c + 2 > u)
+                            cmat_fold_slot(&col[(c4.z & (kCmat - 1)) * kWave], WIDEST ? -x.z : x.z, c + 2);
+                        cmat_fold_slot(&col[(c4.w & (kCmat - 1)) * kWave], WIDEST ? -x.w : x.w, c + 3);
+                    }
                 }
-                if (c0 + 1 > u) {
-                    cmat_fold_slot(&col[(c4.y & (kCmat - 1)) * kWave], WIDEST ? -x.y : x.y, c0 + 1);
-                }
-                if (c0 + 2 > u) {
-                    cmat_fold_slot(&col[(c4.z & (kCmat - 1)) * kWave], WIDEST ? -x.z : x.z, c0 + 2);
-                }
-                cmat_fold_slot(&col[(c4.w & (kCmat - 1)) * kWave], WIDEST ? -x.w : x.w, c0 + 3);
-                x = xn;
-                c4 = cn;
             }
         } else {
             for (int c = u + 1 + lane; c < n; c += kWave) {
@@ -586,35 +599,38 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
             if (r) v_par[u] = NIL;
         }
         __syncthreads();
-        // component = root of the hook forest, by pointer jumping
-        for (int it = 0; it < 64; ++it) {
-            if (t == 0) s_flag[1] = 0;
-            __syncthreads();
-            bool ch = false;
-            for (int u0 = t; u0 < n; u0 += kB * kRoundThreads) {
-                int c[kB], cc[kB];
+        // component = root of the hook forest.  Every vertex follows its chain
+        // of hook targets up to the root (which holds itself), storing each
+        // step in its own entry, so that chains through it shorten for the
+        // other threads.  An entry read mid-update holds an earlier or later
+        // point of the same chain, so every thread reaches the same root; the
+        // forest is acyclic (edge keys are distinct, mutual pairs were broken
+        // above), which bounds every chain by n.
+        for (int u0 = t; u0 < n; u0 += kB * kRoundThreads) {
+            int c[kB];
 #pragma unroll
-                for (int j = 0; j < kB; ++j) {
-                    const int u = u0 + j * kRoundThreads;
-                    c[j] = u < n ? v_comp[u] : 0;
-                }
+            for (int j = 0; j < kB; ++j) {
+                const int u = u0 + j * kRoundThreads;
+                c[j] = u < n ? v_comp[u] : 0;  // vertex 0's chain stands in past n
+            }
+            bool more = true;
+            for (int it = 0; more && it < n; ++it) {
+                int cc[kB];
 #pragma unroll
                 for (int j = 0; j < kB; ++j) cc[j] = v_comp[c[j]];
+                more = false;
 #pragma unroll
                 for (int j = 0; j < kB; ++j) {
                     const int u = u0 + j * kRoundThreads;
-                    if (u < n && cc[j] != c[j]) {
-                        v_comp[u] = (uint16_t)cc[j];
-                        ch = true;
+                    if (cc[j] != c[j]) {
+                        c[j] = cc[j];
+                        if (u < n) v_comp[u] = (uint16_t)cc[j];
+                        more = true;
                     }
                 }
             }
-            if (ch) s_flag[1] = 1;
-            __syncthreads();
-            const int again = s_flag[1];
-            __syncthreads();
-            if (!again) break;
         }
+        __syncthreads();
         // dense numbers: id(root r) = number of roots below r, from a bitmap of
         // the roots (64 per word) and the exclusive prefix of its word counts
         uint64_t* bits = s_dyn;  // n/64 words, then n/64 prefix counts

@@ -65,8 +65,8 @@ def alg_bytes_per_launch(kernel, n, launches=1.0, stats=None):
         tables = stats.get("tables", 0)      # a component-table pass its upper triangle
         lists = max(stats.get("passes", 1) - 1 - tables, 0)
         return (4.0 * n * n * lists + 2.0 * n * (n - 1) * tables) / launches
-    if kernel == "tree_rounds_kernel":       # candidate lists (32 B per 4 entries) + labels
-        return (8.0 * K_LIST + 12.0) * n * stats.get("passes", launches) / launches
+    if kernel == "tree_rounds_kernel":       # candidate lists (2-byte id + 4-byte weight
+        return (6.0 * K_LIST + 12.0) * n * stats.get("passes", launches) / launches  # each) + labels
     return None
 
 

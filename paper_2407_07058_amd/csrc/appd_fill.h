@@ -63,61 +63,85 @@ __device__ __forceinline__ void fill_prep_block(const int32_t* __restrict__ pos,
                                                 uint32_t* bits, int32_t* wpre, uint64_t* gap,
                                                 uint64_t* srt) {
     static_assert(CB + 16 <= (1 << kCodeShift), "slot codes must fit");
+    static_assert(CB % kWave == 0 && CB / kWave <= kWave, "one wave scans the wave totals");
+    const int t = threadIdx.x;  // blockDim.x == CB: one column (and one gap) per thread
+    const int lane = t & (kWave - 1), wid = t / kWave;
     const int j0 = blk * CB;
     const int cnt = min(CB, n - j0);
     const int nw = (n + 31) / 32;
-    for (int c = threadIdx.x; c < CB; c += blockDim.x) gap[c] = 0;
-    for (int w = threadIdx.x; w < nw; w += blockDim.x) bits[w] = 0;
+    const int pm = t < cnt ? pos[j0 + t] : -1;  // this thread's column's position
+    gap[t] = 0;
+    for (int w = t; w < nw; w += CB) bits[w] = 0;
     __syncthreads();
     // the block's positions as a bitmap over 0..n-1
-    for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
-        const int p = pos[j0 + c];
-        atomicOr(&bits[p >> 5], 1u << (p & 31));
-    }
+    if (pm >= 0) atomicOr(&bits[pm >> 5], 1u << (pm & 31));
     __syncthreads();
-    // exclusive prefix of the word counts (one thread per run of words)
-    const int per = (nw + (int)blockDim.x - 1) / (int)blockDim.x;
-    const int w0 = min(nw, (int)threadIdx.x * per), w1 = min(nw, w0 + per);
+    // exclusive prefix of the word counts: each thread counts a run of words,
+    // then a block scan of the run counts (shuffles within each wave, one wave
+    // over the wave totals)
+    const int per = (nw + CB - 1) / CB;
+    const int w0 = min(nw, t * per), w1 = min(nw, w0 + per);
     int c = 0;
     for (int w = w0; w < w1; ++w) c += __popc(bits[w]);
-    // exclusive scan of the threads' counts (Hillis-Steele in LDS; up to 1024
-    // threads)
-    __shared__ int s_cnt[1024];
-    s_cnt[threadIdx.x] = c;
-    __syncthreads();
-    for (int d = 1; d < (int)blockDim.x; d <<= 1) {
-        const int y = (int)threadIdx.x >= d ? s_cnt[threadIdx.x - d] : 0;
-        __syncthreads();
-        s_cnt[threadIdx.x] += y;
-        __syncthreads();
+    __shared__ int s_tot[CB / kWave];
+    int incl = c;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
     }
-    int run = s_cnt[threadIdx.x] - c;
+    if (lane == kWave - 1) s_tot[wid] = incl;
+    __syncthreads();
+    if (wid == 0) {
+        const int v = lane < CB / kWave ? s_tot[lane] : 0;
+        int x = v;
+#pragma unroll
+        for (int d = 1; d < CB / kWave; d <<= 1) {
+            const int y = __shfl_up(x, d);
+            if (lane >= d) x += y;
+        }
+        if (lane < CB / kWave) s_tot[lane] = x - v;
+    }
+    __syncthreads();
+    int run = s_tot[wid] + incl - c;
     for (int w = w0; w < w1; ++w) {
         wpre[w] = run;
         run += __popc(bits[w]);
     }
     __syncthreads();
     // slot of column c = rank of its position among the block's positions
-    for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
-        const int p = pos[j0 + c];
-        const int k = wpre[p >> 5] + __popc(bits[p >> 5] & ((1u << (p & 31)) - 1u));
-        keys[k] = ((uint32_t)p << 16) | (uint32_t)c;
-        blk_sp[j0 + k] = (uint16_t)p;
-        blk_slot[j0 + c] = (uint16_t)k;
+    if (pm >= 0) {
+        const int k = wpre[pm >> 5] + __popc(bits[pm >> 5] & ((1u << (pm & 31)) - 1u));
+        keys[k] = ((uint32_t)pm << 16) | (uint32_t)t;
+        blk_sp[j0 + k] = (uint16_t)pm;
+        blk_slot[j0 + t] = (uint16_t)k;
     }
     __syncthreads();
-    // one sweep over ek: position p > sp[0] lies in slot k = #{sp < p}
+    // one sweep over ek: position p > sp[0] lies in slot k = #{sp < p}; the
+    // loads of a batch are issued before its atomics
     const int lo = (int)(keys[0] >> 16) + 1, hi = (int)(keys[cnt - 1] >> 16);
-    for (int p = lo + (int)threadIdx.x; p <= hi; p += blockDim.x) {
-        const int k = wpre[p >> 5] + __popc(bits[p >> 5] & ((1u << (p & 31)) - 1u));
-        atomicMax((unsigned long long*)&gap[k], (unsigned long long)ek[p]);
+    constexpr int kSweep = 8;
+    for (int p0 = lo + t; p0 <= hi; p0 += kSweep * CB) {
+        uint64_t e[kSweep];
+#pragma unroll
+        for (int i = 0; i < kSweep; ++i) {
+            const int p = p0 + i * CB;
+            e[i] = p <= hi ? ek[p] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < kSweep; ++i) {
+            const int p = p0 + i * CB;
+            if (p <= hi) {
+                const int k = wpre[p >> 5] + __popc(bits[p >> 5] & ((1u << (p & 31)) - 1u));
+                atomicMax((unsigned long long*)&gap[k], (unsigned long long)e[i]);
+            }
+        }
     }
     __syncthreads();
     // sorted gaps (slots 1..cnt-1), padded with the largest key: bitonic sort
     // with one key per thread (blockDim.x == CB); exchanges at strides below
     // the wave width go through shuffles, the others through LDS
     {
-        const int t = threadIdx.x;
         uint64_t x = (t + 1 < cnt) ? gap[t + 1] : ~0ull;
         for (int size = 2; size <= CB; size <<= 1) {
             for (int stride = size >> 1; stride > 0; stride >>= 1) {

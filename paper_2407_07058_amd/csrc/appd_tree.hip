@@ -676,15 +676,31 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
             if (small) t_best[d] = t_lb[d] = kNone;
             else a.best[d] = a.lb[d] = kNone;
         }
-    } else {
-        for (int v = t; v < n; v += kRoundThreads) {
-            if (LDS) {
-                setc(v, first ? v : a.comp[v]);
-                setp(v, first ? -1 : a.par[v]);
-            } else if (first) {
-                a.par[v] = -1;
+    } else if (LDS) {
+        // the forest so far into LDS, eight vertices per thread at a time
+        constexpr int kB = 8;
+        for (int v0 = t; v0 < n; v0 += kB * kRoundThreads) {
+            int c[kB], p[kB];
+#pragma unroll
+            for (int j = 0; j < kB; ++j) {
+                const int v = v0 + j * kRoundThreads;
+                c[j] = v < n ? (first ? v : a.comp[v]) : 0;
+                p[j] = v < n ? (first ? -1 : a.par[v]) : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < kB; ++j) {
+                const int v = v0 + j * kRoundThreads;
+                if (v < n) {
+                    setc(v, c[j]);
+                    setp(v, p[j]);
+                }
             }
         }
+        if (small)
+            for (int d = t; d < C; d += kRoundThreads) t_best[d] = t_lb[d] = kNone;
+    } else {
+        if (first)
+            for (int v = t; v < n; v += kRoundThreads) a.par[v] = -1;
         if (small)
             for (int d = t; d < C; d += kRoundThreads) t_best[d] = t_lb[d] = kNone;
     }

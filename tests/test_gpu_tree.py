@@ -36,7 +36,7 @@ def check(W, mode=appd.MINIMAX):
     assert np.array_equal(M.view(np.uint32), Mo.view(np.uint32)) and np.array_equal(idx, io)
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 17, 64, 100, 257, 1000, 1025, 3000])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 17, 64, 100, 257, 1000, 1025, 3000, 4097, 6001])
 def test_boruvka_random(n):
     say("case boruvka random n=%d" % n)
     check(workloads.random_symmetric(n, seed=n + 1))

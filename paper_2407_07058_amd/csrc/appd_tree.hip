@@ -1034,6 +1034,16 @@ __global__ __launch_bounds__(kRoundThreads) void tree_rounds_kernel(RoundArgs a)
 // (else the sequential fallback produced the outputs).  One thread per vertex
 // wherever the work is independent, so each dependent chain is paid once.
 
+// Workgroups are dispatched to the eight XCDs in turn and each XCD has its own
+// L2.  A kernel launched kXcds times wider, in which only every kXcds-th
+// workgroup works, keeps all its work on one XCD: a line that many threads'
+// pointer chains share is then fetched into one L2 once and hit there, not
+// missed once per XCD.  Only the speed depends on the dispatch order.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block() {
+    return blockIdx.x % kXcds ? -1 : (int)(blockIdx.x / kXcds);
+}
+
 // Edge key to the parent, link initialised to the parent.
 template <bool WIDEST>
 __device__ __forceinline__ void keyup_vertex(const float* __restrict__ W, int n, const int32_t* par,
@@ -1084,12 +1094,14 @@ __device__ __forceinline__ void add_folded(int32_t* arr, int target) {
 // link[] entry holds at any time is an ancestor reached over smaller edges
 // only, so a thread may follow entries other threads are still updating, and
 // it publishes its own progress as it goes.  Every jump moves up the tree, so
-// each thread ends.
+// each thread ends.  The chains share the upper part of the tree, so the
+// kernel runs on one XCD (xcd_block; n = 8192: 20 -> 13 us).
 __global__ __launch_bounds__(256) void tree_link_kernel(int n, const uint64_t* keyup,
                                                        int32_t* link, int32_t* gcount,
                                                        const int32_t* ctrl) {
-    if (!ctrl[C_ORDERED]) return;
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int bid = xcd_block();
+    if (bid < 0 || !ctrl[C_ORDERED]) return;
+    const int v = bid * blockDim.x + threadIdx.x;
     if (v == 0 || v >= n) return;
     const uint64_t kv = keyup[v];
     int c = link[v];
@@ -1583,7 +1595,7 @@ static hipError_t run_tree_parallel_t(const float* W, int n, PrimOut out, void* 
     e = launch_finish<WIDEST>(W, n, out, w, s);
     if (e != hipSuccess) return e;
     APPD_LAUNCH("tree_link_kernel", s,
-        tree_link_kernel<<<nb, 256, 0, s>>>(n, w.keyup, w.link, w.gcount, w.ctrl));
+        tree_link_kernel<<<nb * kXcds, 256, 0, s>>>(n, w.keyup, w.link, w.gcount, w.ctrl));
     APPD_CHK();
     // the packed (size, arrivals) words go to lb, free by now
     const int nsb = (n + kScanBlock - 1) / kScanBlock;
@@ -1728,7 +1740,7 @@ hipError_t run_linkage(const float* W, int n, int mode, const PrimOut& out, void
                 w.gcount, w.hook, nullptr, w.ctrl));
     APPD_CHK_L();
     APPD_LAUNCH("tree_link_kernel", s,
-        tree_link_kernel<<<nb, 256, 0, s>>>(n, w.keyup, w.link, w.gcount, w.ctrl));
+        tree_link_kernel<<<nb * kXcds, 256, 0, s>>>(n, w.keyup, w.link, w.gcount, w.ctrl));
     APPD_CHK_L();
     APPD_LAUNCH("tree_sizes_kernel", s,
         tree_sizes_kernel<<<nb, 256, 0, s>>>(n, w.link, w.size, w.gcount, w.hook, w.ctrl));

@@ -154,7 +154,11 @@ int appd_linkage(const float* W, int n, int mode, double* Z, void* ws, size_t ws
  * class runs Prim's algorithm (one workgroup per graph, class_threads[c]
  * threads) and then the fill (work items of class_rows[c] rows); up to
  * `streams` classes proceed concurrently on library streams forked from and
- * joined back into `stream`.
+ * joined back into `stream` (the largest class alone on `stream`, the others
+ * in turn on the library streams; with split_count, the largest class's
+ * biggest graphs alone on `stream` and the rest of it on the first library
+ * stream, so that its smaller graphs' fill runs beside the longest Prim
+ * chains).
  *
  * appd_batch_prepare plans the batch on the host (default schedule) and copies
  * the tables into ws with synchronous host-to-device copies; it must precede
@@ -183,6 +187,10 @@ typedef struct {
     int grad_chunks;  /* work items of the edge-gradient kernel */
     int chain_blocks; /* work items of the point-gradient kernel */
     size_t ws_bytes;  /* workspace the batch needs */
+    int split_count;  /* with streams >= 2: the largest class's first split_count graphs
+                         (its largest) run as a launch pair of their own on `stream`,
+                         the rest of the class on a library stream; 0: one launch pair */
+    int split_chunks; /* fill work items of those graphs (set with split_count) */
 } appd_batch_plan;
 
 /* Workspace bytes for a batch with these sizes (0 on invalid input). */

@@ -79,7 +79,8 @@ class BatchPlan(ctypes.Structure):
                 ("class_threads", ctypes.c_int * BATCH_CLASSES),
                 ("streams", ctypes.c_int), ("pair_tiles", ctypes.c_int),
                 ("grad_chunks", ctypes.c_int), ("chain_blocks", ctypes.c_int),
-                ("ws_bytes", ctypes.c_size_t)]
+                ("ws_bytes", ctypes.c_size_t), ("split_count", ctypes.c_int),
+                ("split_chunks", ctypes.c_int)]
 
 _lib = None
 

@@ -98,11 +98,20 @@ appd::BatchPlan device_plan(const appd_batch_plan* p, const Tables& t) {
         bp.class_threads[c] = p->class_threads[c];
     }
     bp.streams = p->streams;
+    bp.split_count = p->split_count;
+    bp.split_chunks = p->split_chunks;
     return bp;
 }
 
 bool schedule_ok(const appd_batch_plan* p) {
     if (p->streams < 1 || p->streams > appd::kBatchClasses) return false;
+    int top = -1;  // the largest class present
+    for (int c = 0; c < appd::kBatchClasses; ++c)
+        if (p->class_count[c]) top = c;
+    if (p->split_count < 0 || p->split_chunks < 0) return false;
+    if (p->split_count && (top < 0 || p->split_count >= p->class_count[top] ||
+                           p->split_chunks < 1 || p->split_chunks >= p->class_chunks[top]))
+        return false;
     for (int c = 0; c < appd::kBatchClasses; ++c) {
         if (!p->class_count[c]) continue;
         if (p->class_rows[c] < 1 || p->class_rows[c] > APPD_BATCH_MAX_N) return false;
@@ -112,9 +121,13 @@ bool schedule_ok(const appd_batch_plan* p) {
 }
 
 // Fill work items per class for the plan's rows per item; chunk_start[i] is the
-// first item of the i-th graph (n-descending order) within its class.
+// first item of the i-th graph (n-descending order) within its class.  With
+// split, the largest class is cut after its graphs of n >= 0.84 n_max: a Prim
+// chain grows with n and a fill with n^2, and for sizes spread evenly on a log
+// scale over one class (n_max / 2, n_max] this cut gives the two parts about
+// the same Prim + fill time.
 void build_chunks(const int32_t* ns_host, const std::vector<int32_t>& perm, appd_batch_plan* p,
-                  std::vector<int32_t>& chunk_start) {
+                  std::vector<int32_t>& chunk_start, bool split) {
     const int G = p->num_graphs;
     chunk_start.assign(G, 0);
     for (int c = 0; c < appd::kBatchClasses; ++c) p->class_chunks[c] = 0;
@@ -124,6 +137,20 @@ void build_chunks(const int32_t* ns_host, const std::vector<int32_t>& perm, appd
         const int rows = p->class_rows[c];
         chunk_start[i] = p->class_chunks[c];
         p->class_chunks[c] += (n + rows - 1) / rows;
+    }
+    p->split_count = p->split_chunks = 0;
+    int top = -1;
+    for (int c = 0; c < appd::kBatchClasses; ++c)
+        if (p->class_count[c]) top = c;
+    if (!split || top < 0) return;
+    const int first = p->class_first[top], count = p->class_count[top];
+    const int nmax = ns_host[perm[first]];
+    int h = 0;
+    while (h < count && 100 * (int64_t)ns_host[perm[first + h]] >= 84 * (int64_t)nmax) ++h;
+    if (h > 0 && h < count && chunk_start[first + h] > 0 &&
+        chunk_start[first + h] < p->class_chunks[top]) {
+        p->split_count = h;
+        p->split_chunks = chunk_start[first + h];
     }
 }
 
@@ -207,7 +234,7 @@ int appd_batch_prepare(const int32_t* ns_host, int num_graphs, void* ws, size_t 
     for (int c = 0; c < appd::kBatchClasses; ++c)
         if (p.class_first[c] < 0) p.class_first[c] = 0;
     default_schedule(&p);
-    build_chunks(ns_host, perm, &p, chunk_start);
+    build_chunks(ns_host, perm, &p, chunk_start, false);
 
     // one host image of the table region, one synchronous copy
     std::vector<char> img(lay.table_bytes, 0);
@@ -256,19 +283,21 @@ int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan*
     static const int narrow[appd::kBatchClasses] = {64, 64, 64, 256, 256, 256};
     static const int wide[appd::kBatchClasses] = {64, 128, 256, 512, 512, 1024};
     static const int rows_opt[3] = {16, 32, 64};
-    static const int streams_opt[2] = {1, 3};
+    static const int streams_opt[4] = {1, 3, 4, 5};
     appd_batch_plan best = *plan;
     float best_t = -1.f;
     for (int wsel = 0; wsel < 2; ++wsel)
         for (int ri = 0; ri < 3; ++ri)
-            for (int si = 0; si < 2; ++si) {
+            for (int si = 0; si < 4; ++si)
+              for (int sp = 0; sp < 2; ++sp) {
+                if (sp && streams_opt[si] == 1) continue;  // a split needs two streams
                 appd_batch_plan p = *plan;
                 for (int c = 0; c < appd::kBatchClasses; ++c) {
                     p.class_threads[c] = wsel ? wide[c] : narrow[c];
                     p.class_rows[c] = rows_opt[ri];
                 }
                 p.streams = streams_opt[si];
-                build_chunks(ns.data(), perm, &p, chunk_start);
+                build_chunks(ns.data(), perm, &p, chunk_start, sp != 0);
                 if ((e = hipStreamSynchronize(s)) != hipSuccess ||
                     (e = hipMemcpy(t.chunk_start, chunk_start.data(), 4 * (size_t)G,
                                    hipMemcpyHostToDevice)) != hipSuccess)
@@ -292,7 +321,7 @@ int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan*
                     best = p;
                 }
             }
-    build_chunks(ns.data(), perm, &best, chunk_start);
+    build_chunks(ns.data(), perm, &best, chunk_start, best.split_count > 0);
     if ((e = hipMemcpy(t.chunk_start, chunk_start.data(), 4 * (size_t)G,
                        hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e);

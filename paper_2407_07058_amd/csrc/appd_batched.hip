@@ -9,7 +9,8 @@
 // launch and one fill launch in order on one stream; classes are spread over
 // up to plan.streams streams (forked from and joined back into the caller's
 // stream with events), so the short classes' Prim and fill run beside the
-// longest class's Prim chains.
+// longest class's Prim chains: the largest class alone on the caller's
+// stream, the others in turn on the side streams.
 //
 // Phase 1, one workgroup per graph: Prim (appd_prim.h) with the class's
 // workgroup size (plan.class_threads) and ceil(class max / threads) vertices
@@ -48,15 +49,17 @@ template <int CB, bool WIDEST>
 __global__ __launch_bounds__(kBatchFillThreads) void fill_batched_kernel(
     const int64_t* __restrict__ offsets, const int32_t* __restrict__ ns,
     const int32_t* __restrict__ perm, const int64_t* __restrict__ noff,
-    const int32_t* __restrict__ chunk_start, int first, int count, int rows, BatchTree tree,
-    float* __restrict__ M, int32_t* __restrict__ idx) {
+    const int32_t* __restrict__ chunk_start, int first, int count, int chunk_base, int rows,
+    BatchTree tree, float* __restrict__ M, int32_t* __restrict__ idx) {
     constexpr int NWV = kBatchFillThreads / kWave;
     __shared__ uint16_t s_sp[CB];
     __shared__ __align__(16) uint16_t s_slot[CB];
     __shared__ uint64_t s_gap[CB];
     __shared__ uint64_t s_R[NWV][CB];
-    // which graph of this class, and which chunk of its rows
-    const int b = blockIdx.x;
+    // which graph of this class, and which chunk of its rows (chunk numbers
+    // count from the class's first graph; this launch covers graphs
+    // first .. first + count - 1, from chunk chunk_base on)
+    const int b = chunk_base + (int)blockIdx.x;
     int lo = 0, hi = count - 1;
     while (lo < hi) {  // last gi with chunk_start[first+gi] <= b
         const int mid = (lo + hi + 1) >> 1;
@@ -135,7 +138,8 @@ static hipError_t launch_prim_class(int c, int threads, int first, int count, co
 }
 
 template <bool WIDEST>
-static hipError_t launch_fill_class(int c, int first, int count, int chunks, int rows,
+static hipError_t launch_fill_class(int c, int first, int count, int chunk_base, int chunks,
+                                    int rows,
                                     const int64_t* offsets, const int32_t* ns,
                                     const BatchPlan& plan, const BatchTree& tree, float* M,
                                     int32_t* idx, hipStream_t s) {
@@ -144,7 +148,7 @@ static hipError_t launch_fill_class(int c, int first, int count, int chunks, int
         APPD_LAUNCH("fill_batched_kernel", s,                                         \
                     fill_batched_kernel<CB, WIDEST><<<chunks, kBatchFillThreads, 0, s>>>( \
                         offsets, ns, plan.perm, plan.noff, plan.chunk_start, first,   \
-                        count, rows, tree, M, idx));                                  \
+                        count, chunk_base, rows, tree, M, idx));                      \
         return hipGetLastError();                                                     \
     }
     APPD_FILL_B(0, 64)
@@ -212,15 +216,40 @@ static hipError_t run_batched_t(const float* W, const int64_t* offsets, const in
             if ((e = hipStreamWaitEvent(st[k], ss->fork, 0)) != hipSuccess) return e;
         }
     }
+    // The largest class (the longest Prim chains and most of the entries) has
+    // the caller's stream to itself; the others take the side streams in turn,
+    // so that they finish while it still runs.  Split, the largest class's
+    // biggest graphs keep the caller's stream, the rest of it takes the first
+    // side stream, and the other classes the side streams after it.
+    const bool split = nstreams >= 2 && plan.split_count > 0;
+    const int others0 = split && nstreams >= 3 ? 2 : 1;
     for (int j = 0; j < nc; ++j) {
         const int c = cls[j];
-        hipStream_t cs = st[j % nstreams];
         const int first = plan.class_first[c], count = plan.class_count[c];
+        const int rows = plan.class_rows[c], chunks = plan.class_chunks[c];
+        if (j == 0 && split) {
+            const int h = plan.split_count, hc = plan.split_chunks;
+            e = launch_prim_class<WIDEST>(c, plan.class_threads[c], first, h, W, offsets, ns,
+                                          plan, tree, st[0]);
+            if (e != hipSuccess) return e;
+            e = launch_fill_class<WIDEST>(c, first, h, 0, hc, rows, offsets, ns, plan, tree, M,
+                                          idx, st[0]);
+            if (e != hipSuccess) return e;
+            e = launch_prim_class<WIDEST>(c, plan.class_threads[c], first + h, count - h, W,
+                                          offsets, ns, plan, tree, st[1]);
+            if (e != hipSuccess) return e;
+            e = launch_fill_class<WIDEST>(c, first + h, count - h, hc, chunks - hc, rows,
+                                          offsets, ns, plan, tree, M, idx, st[1]);
+            if (e != hipSuccess) return e;
+            continue;
+        }
+        hipStream_t cs =
+            (j == 0 || nstreams == 1) ? st[0] : st[others0 + (j - 1) % (nstreams - others0)];
         e = launch_prim_class<WIDEST>(c, plan.class_threads[c], first, count, W, offsets, ns,
                                       plan, tree, cs);
         if (e != hipSuccess) return e;
-        e = launch_fill_class<WIDEST>(c, first, count, plan.class_chunks[c], plan.class_rows[c],
-                                      offsets, ns, plan, tree, M, idx, cs);
+        e = launch_fill_class<WIDEST>(c, first, count, 0, chunks, rows, offsets, ns, plan, tree,
+                                      M, idx, cs);
         if (e != hipSuccess) return e;
     }
     if (nstreams > 1) {

@@ -78,6 +78,8 @@ struct BatchPlan {
     int class_rows[kBatchClasses];
     int class_threads[kBatchClasses];
     int streams;
+    int split_count;   // largest class: graphs launched first on their own (0: no split)
+    int split_chunks;  // their fill work items
 };
 
 int batch_class_of(int n);

@@ -165,6 +165,39 @@ def test_batched_schedules_identical():
         assert torch.equal(M, M0) and torch.equal(I, I0), (threads, streams)
 
 
+def test_batched_split_largest_class():
+    """The largest class cut in two launch pairs on two streams (its biggest
+    graphs, then the rest from a chunk offset) gives the same bits as the
+    default schedule, at several cuts and stream counts; an out-of-range cut is
+    rejected before any launch."""
+    say("case batched split of the largest class")
+    Ws = mixed_graphs(8)
+    flat, offsets, ns = workloads.pack(Ws)
+    Wd = torch.from_numpy(flat).to(DEV)
+    M0, I0 = appd.Batch(ns, DEV).forward(Wd)
+    torch.cuda.synchronize()
+    ns = np.asarray(ns)
+    cls = np.array([next(c for c in range(appd.BATCH_CLASSES) if n <= 64 << c) for n in ns])
+    top = int(cls.max())
+    members = np.sort(ns[cls == top])[::-1]  # the class in launch order (n descending)
+    assert len(members) >= 2, members
+    for h, streams in [(1, 2), (len(members) // 2, 3), (len(members) - 1, 5)]:
+        b = appd.Batch(ns, DEV)
+        rows = b.plan.class_rows[top]
+        b.plan.streams = streams
+        b.plan.split_count = int(h)
+        b.plan.split_chunks = int(sum((int(n) + rows - 1) // rows for n in members[:h]))
+        M, I = b.forward(Wd)
+        torch.cuda.synchronize()
+        assert torch.equal(M, M0) and torch.equal(I, I0), (h, streams)
+    b = appd.Batch(ns, DEV)
+    b.plan.streams = 3
+    b.plan.split_count = len(members)
+    b.plan.split_chunks = 1
+    with pytest.raises(appd.APPDError):
+        b.forward(Wd)
+
+
 def test_batched_autotune_bit_exact():
     """The autotuner picks a schedule by timing; whatever it picks, every graph
     still equals the oracle."""

@@ -283,12 +283,15 @@ int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan*
     static const int narrow[appd::kBatchClasses] = {64, 64, 64, 256, 256, 256};
     static const int wide[appd::kBatchClasses] = {64, 128, 256, 512, 512, 1024};
     static const int rows_opt[3] = {16, 32, 64};
-    static const int streams_opt[4] = {1, 3, 4, 5};
+    // at most 4 streams: a process gets 4 hardware queues by default, and a
+    // fifth stream shares one with another (a kernel trace of a HIP-graph
+    // replay showed a small class queued behind the largest one)
+    static const int streams_opt[3] = {1, 3, 4};
     appd_batch_plan best = *plan;
     float best_t = -1.f;
     for (int wsel = 0; wsel < 2; ++wsel)
         for (int ri = 0; ri < 3; ++ri)
-            for (int si = 0; si < 4; ++si)
+            for (int si = 0; si < 3; ++si)
               for (int sp = 0; sp < 2; ++sp) {
                 if (sp && streams_opt[si] == 1) continue;  // a split needs two streams
                 appd_batch_plan p = *plan;

@@ -293,10 +293,41 @@ __device__ __forceinline__ void fill_rows_block(const int32_t* __restrict__ pos,
                 *(int4*)(irow + c) = iv;
             }
         } else {
-            for (int c = lane; c < cnt; c += kWave) {
+            auto put1 = [&](int c) {
                 const uint64_t key = s_R[s_slot[c]];
                 mrow[c] = key ? key_weight<WIDEST>(key) : 0.0f;
                 irow[c] = key ? (int32_t)(uint32_t)key : -1;
+            };
+            // A row may start at any 4-byte boundary (graphs packed back to
+            // back).  When the M and idx rows are aligned alike: the columns
+            // up to the first 16-byte boundary and the last (cnt - h) % 4 one
+            // lane each, the rest four columns per 16-byte store.
+            const int mis = (int)(((uintptr_t)mrow >> 2) & 3u);
+            if (mis == (int)(((uintptr_t)irow >> 2) & 3u)) {
+                const int h = min(cnt, (4 - mis) & 3);
+                const int nq = (cnt - h) >> 2;
+                const int tail0 = h + 4 * nq;
+                if (lane < h) put1(lane);
+                if (lane < cnt - tail0) put1(tail0 + lane);
+                for (int m = lane; m < nq; m += kWave) {
+                    const int c = h + 4 * m;
+                    const uint64_t k0v = s_R[s_slot[c]], k1v = s_R[s_slot[c + 1]];
+                    const uint64_t k2v = s_R[s_slot[c + 2]], k3v = s_R[s_slot[c + 3]];
+                    float4 mv;
+                    int4 iv;
+                    mv.x = k0v ? key_weight<WIDEST>(k0v) : 0.0f;
+                    mv.y = k1v ? key_weight<WIDEST>(k1v) : 0.0f;
+                    mv.z = k2v ? key_weight<WIDEST>(k2v) : 0.0f;
+                    mv.w = k3v ? key_weight<WIDEST>(k3v) : 0.0f;
+                    iv.x = k0v ? (int32_t)(uint32_t)k0v : -1;
+                    iv.y = k1v ? (int32_t)(uint32_t)k1v : -1;
+                    iv.z = k2v ? (int32_t)(uint32_t)k2v : -1;
+                    iv.w = k3v ? (int32_t)(uint32_t)k3v : -1;
+                    *(float4*)(mrow + c) = mv;
+                    *(int4*)(irow + c) = iv;
+                }
+            } else {
+                for (int c = lane; c < cnt; c += kWave) put1(c);
             }
         }
         wave_lds_sync();

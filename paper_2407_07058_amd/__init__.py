@@ -264,10 +264,12 @@ class Batch:
         return ms.value
 
     def schedule(self) -> dict:
-        """The plan's per-class schedule (classes n <= 64 .. 2048)."""
+        """The plan's per-class schedule (classes n <= 64 .. 2048); split_count:
+        graphs of the largest class launched on their own (0: not cut)."""
         p = self.plan
         return {"class_count": list(p.class_count), "class_threads": list(p.class_threads),
-                "class_rows": list(p.class_rows), "streams": p.streams}
+                "class_rows": list(p.class_rows), "streams": p.streams,
+                "split_count": p.split_count}
 
     def forward(self, W: torch.Tensor, mode: int = MINIMAX, return_parent: bool = False,
                 out=None):

@@ -10,6 +10,7 @@ import torch
 import oracle
 import paper_2407_07058_amd as appd
 import workloads
+from gpu_helpers import assert_matches_digest, uniform32768_reference
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -96,21 +97,24 @@ def test_boruvka_equals_prim_mixture_full():
     assert np.array_equal(a[0].view(np.uint32), Mo.view(np.uint32)) and np.array_equal(a[1], io)
 
 
-@pytest.mark.timeout(400)
-def test_boruvka_uniform_full_sampled():
-    n = 32768
-    say("case boruvka uniform n=32768: generate")
-    W = workloads.config_uniform(n)
-    say("case boruvka uniform n=32768: forward (boruvka, prim)")
+@pytest.mark.timeout(600)
+def test_uniform_full_boruvka_and_prim():
+    """n = 32768 uniform weights, forced Borůvka tree and forced Prim tree: the
+    attachment order and parents equal the oracle's Prim, and every row slab of
+    M and idx has the SHA-256 of the oracle's full output."""
+    say("case uniform n=32768: generate")
+    W, ref = uniform32768_reference()
     Wd = torch.from_numpy(W).to(DEV)
-    Ma, Ia, oa, pa = appd.forward(Wd, return_tree=True, tree="boruvka")
-    torch.cuda.synchronize()
     o, p, _, _ = oracle.mst_prim(W)
-    assert np.array_equal(oa.cpu().numpy(), o) and np.array_equal(pa.cpu().numpy(), p)
-    rows = np.arange(0, n, 997)
-    Mo, io = oracle.appd_rows(W, rows)
-    assert np.array_equal(Ma[rows].cpu().numpy().view(np.uint32), Mo.view(np.uint32))
-    assert np.array_equal(Ia[rows].cpu().numpy(), io)
+    for tree in ("boruvka", "prim"):
+        say("case uniform n=32768: forward tree=%s" % tree)
+        Ma, Ia, oa, pa = appd.forward(Wd, return_tree=True, tree=tree)
+        torch.cuda.synchronize()
+        assert np.array_equal(oa.cpu().numpy(), o) and np.array_equal(pa.cpu().numpy(), p)
+        say("case uniform n=32768: slab digests tree=%s" % tree)
+        assert_matches_digest(Ma, Ia, ref, tree)
+        del Ma, Ia
+        torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("k,mode", [(3, appd.MINIMAX), (12, appd.MINIMAX), (12, appd.WIDEST)])

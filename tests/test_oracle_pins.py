@@ -343,6 +343,73 @@ def test_pairwise_euclidean(orc):
     assert np.allclose(W, W64, rtol=4e-7, atol=0)
 
 
+def _euclid_f32_numpy(X):
+    """The float32 distance evaluated by numpy, one IEEE float32 rounding per
+    operation: subtract, square, add in increasing coordinate order, then the
+    correctly rounded square root.  numpy never contracts a*b+c into a fused
+    multiply-add, so this is exactly the operation sequence the oracle states."""
+    X = np.asarray(X, np.float32)
+    n, d = X.shape
+    acc = np.zeros((n, n), np.float32)
+    for t in range(d):
+        diff = X[:, None, t] - X[None, :, t]
+        sq = diff * diff
+        acc = acc + sq
+    W = np.sqrt(acc)
+    W[np.arange(n), np.arange(n)] = 0.0
+    return W
+
+
+@pytest.mark.parametrize("d,scale,seed", [(1, 1.0, 2), (2, 1.0, 3), (8, 1.0, 4), (16, 3.0, 5),
+                                          (5, 1e-19, 6), (7, 1e17, 7)])
+def test_pairwise_euclidean_f32_bit_exact(orc, d, scale, seed):
+    """Bit-for-bit against numpy's float32 evaluation in the same order.  A fused
+    multiply-add, a different summation order, a float64 accumulator or a
+    non-correctly-rounded square root each change some of these bits."""
+    rng = np.random.default_rng(seed)
+    X = (rng.standard_normal((257, d)) * scale).astype(np.float32)
+    W = orc.pairwise_euclidean_f32(X)
+    assert np.array_equal(W.view(np.uint32), _euclid_f32_numpy(X).view(np.uint32))
+
+
+def test_pairwise_euclidean_f32_detects_reordering():
+    """The reference above is sensitive to what the bit-exact pin claims: on this
+    input, summing in decreasing coordinate order, accumulating in float64 or
+    fusing the multiply-add each changes at least one distance."""
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((257, 8)).astype(np.float32)
+    ref = _euclid_f32_numpy(X)
+    rev = _euclid_f32_numpy(X[:, ::-1])
+    assert not np.array_equal(ref, rev)
+    acc64 = np.zeros((257, 257))
+    for t in range(8):
+        df = (X[:, None, t] - X[None, :, t]).astype(np.float64)
+        acc64 += df * df
+    w64 = np.sqrt(acc64).astype(np.float32)
+    np.fill_diagonal(w64, 0)
+    assert not np.array_equal(ref, w64)
+    # a fused multiply-add rounds diff*diff + acc once: emulate it exactly in float64
+    # (products of floats are exact in double, and one rounding to float32 follows)
+    accf = np.zeros((257, 257), np.float32)
+    for t in range(8):
+        df = (X[:, None, t] - X[None, :, t]).astype(np.float64)
+        accf = (df * df + accf.astype(np.float64)).astype(np.float32)
+    wf = np.sqrt(accf)
+    np.fill_diagonal(wf, 0)
+    assert not np.array_equal(ref, wf)
+
+
+def test_pairwise_euclidean_f32_one_dimension(orc):
+    """d = 1: the distance is |x_i - x_j| rounded once, because the correctly
+    rounded square root of a correctly rounded square gives the number back
+    (round to nearest, no overflow or underflow)."""
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((300, 1)).astype(np.float32)
+    W = orc.pairwise_euclidean_f32(x)
+    ref = np.abs(x[:, None, 0] - x[None, :, 0])
+    assert np.array_equal(W.view(np.uint32), ref.view(np.uint32))
+
+
 def _fd_generic(orc, X, G, h=1e-6, ndir=4, seed=0):
     """Directional central differences of the float64 loss, kept only where the
     float64 bottleneck structure does not change within +-h."""

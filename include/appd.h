@@ -74,6 +74,25 @@ enum appd_mode {
 const char* appd_error_string(int code);
 int appd_get_last_error(void);
 
+/*
+ * Optional precondition check of W.  The method is defined on an undirected
+ * graph with edge weights (Section 1: an undirected graph and its weights
+ * e_w), so W must be symmetric; the calls here also ask for a NaN-free W with
+ * a zero diagonal.  One pass over W (every element read once) or-s into
+ * *flags (one uint32 in device memory, cleared by the call itself):
+ *   APPD_VALID_NAN   some entry is NaN
+ *   APPD_VALID_ASYM  some pair of non-NaN mirror entries differ (float compare:
+ *                    -0.0 and +0.0 are equal weights)
+ *   APPD_VALID_DIAG  some diagonal entry is not zero
+ * 0 means every precondition holds.  Stream-ordered like every call: the flags
+ * are valid once `stream` has reached them.  APPD_EINVAL for a null pointer or
+ * n out of range.
+ */
+#define APPD_VALID_NAN 0x1u
+#define APPD_VALID_ASYM 0x2u
+#define APPD_VALID_DIAG 0x4u
+int appd_validate(const float* W, int n, uint32_t* flags, void* stream);
+
 /* Bytes of device workspace appd_forward_ws / appd_forward_ex need for n
  * (0 if n is out of range). */
 size_t appd_forward_workspace_bytes(int n);
@@ -191,6 +210,8 @@ typedef struct {
                          (its largest) run as a launch pair of their own on `stream`,
                          the rest of the class on a library stream; 0: one launch pair */
     int split_chunks; /* fill work items of those graphs (set with split_count) */
+    uint64_t tables_key; /* stamp of the rows per item and cut the device work tables were
+                            built for; a plan whose fields no longer match it is rejected */
 } appd_batch_plan;
 
 /* Workspace bytes for a batch with these sizes (0 on invalid input). */
@@ -206,6 +227,14 @@ int appd_batch_prepare(const int32_t* ns_host, int num_graphs, void* ws, size_t 
  * best_ms (nullable) receives its time per forward. */
 int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan* plan, void* ws,
                         void* stream, float* best_ms);
+
+/* Sets a schedule by hand (for experiments and tests): the plan's
+ * class_threads, class_rows and streams, and split_count (0: no cut, else the
+ * number of the largest class's biggest graphs launched on their own).  The
+ * device work tables are rebuilt for it and the derived fields (class_chunks,
+ * split_chunks, tables_key) set.  Checks the schedule (APPD_EINVAL if it is not
+ * one the kernels support); synchronises and is not capturable. */
+int appd_batch_set_schedule(appd_batch_plan* plan, void* ws, void* stream);
 
 /* Batched forward (Algorithm 4 per graph).  parent: nullable, total_n int32. */
 int appd_forward_batched(const float* W, int mode, float* M, int32_t* idx, int32_t* parent,
@@ -228,6 +257,16 @@ int appd_pairwise_euclidean_batched(const float* X, int d, float* W, const appd_
 int appd_backward_points_batched(const float* X, int d, const float* W, const float* G,
                                  const int32_t* idx, const int32_t* parent, float* dX,
                                  const appd_batch_plan* plan, void* ws, void* stream);
+
+/*
+ * Backward for packed weight-matrix inputs: per graph, dW[idx(i,j)] += G_ij for
+ * i != j (the upper-triangle entry of each pair's bottleneck edge), as
+ * appd_backward_w below.  G, idx and dW are packed like W; parent (total_n
+ * int32) is the forward's.  dW is overwritten: zero except on tree edges.
+ * Float atomics: the summation order, hence the last bits, vary between runs.
+ */
+int appd_backward_w_batched(const float* G, const int32_t* idx, const int32_t* parent, float* dW,
+                            const appd_batch_plan* plan, void* ws, void* stream);
 
 /* ------------------------------------------------------------------ single
  * Single-graph forms of the two calls above.  ws: >= appd_grad_workspace_bytes(n)

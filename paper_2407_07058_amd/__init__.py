@@ -38,6 +38,7 @@ _I = ctypes.c_int
 _SZ = ctypes.c_size_t
 SIGNATURES = {
     "appd_error_string": ([_I], ctypes.c_char_p),
+    "appd_validate": ([_P, _I, _P, _P], _I),
     "appd_get_last_error": ([], _I),
     "appd_forward_workspace_bytes": ([_I], _SZ),
     "appd_forward": ([_P, _I, _P, _P, _P], _I),
@@ -50,6 +51,7 @@ SIGNATURES = {
     "appd_batch_workspace_bytes": ([_P, _I], _SZ),
     "appd_batch_prepare": ([_P, _I, _P, _SZ, _P, _P], _I),
     "appd_forward_batched": ([_P, _I, _P, _P, _P, _P, _P, _P], _I),
+    "appd_batch_set_schedule": ([_P, _P, _P], _I),
     "appd_batch_autotune": ([_P, _P, _P, _P, _P, _P, _P], _I),
     "appd_pairwise_euclidean_batched": ([_P, _I, _P, _P, _P, _P], _I),
     "appd_backward_points_batched": ([_P, _I, _P, _P, _P, _P, _P, _P, _P, _P], _I),
@@ -57,10 +59,15 @@ SIGNATURES = {
     "appd_pairwise_euclidean": ([_P, _I, _I, _P, _P, _SZ, _P], _I),
     "appd_backward_points": ([_P, _I, _I, _P, _P, _P, _P, _P, _P, _SZ, _P], _I),
     "appd_backward_w": ([_P, _P, _P, _I, _P, _P, _SZ, _P], _I),
+    "appd_backward_w_batched": ([_P, _P, _P, _P, _P, _P, _P], _I),
     "appd_timer_start": ([ctypes.c_char_p, _I], _I),
     "appd_timer_read": ([ctypes.c_char_p, _P, _P, _P], _I),
     "appd_timer_names": ([_P, _I], _I),
 }
+
+VALID_NAN = 0x1
+VALID_ASYM = 0x2
+VALID_DIAG = 0x4
 
 BATCH_MAX_N = 2048
 BATCH_CLASSES = 6
@@ -80,7 +87,7 @@ class BatchPlan(ctypes.Structure):
                 ("streams", ctypes.c_int), ("pair_tiles", ctypes.c_int),
                 ("grad_chunks", ctypes.c_int), ("chain_blocks", ctypes.c_int),
                 ("ws_bytes", ctypes.c_size_t), ("split_count", ctypes.c_int),
-                ("split_chunks", ctypes.c_int)]
+                ("split_chunks", ctypes.c_int), ("tables_key", ctypes.c_uint64)]
 
 _lib = None
 
@@ -121,6 +128,40 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _check_tensor(t, name: str, dtype, numel: int, device: torch.device):
+    """Every tensor handed to the library: a contiguous tensor of the given dtype
+    and element count on the given device (the library trusts these)."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+    if t.device != device:
+        raise ValueError("%s is on %s, expected %s" % (name, t.device, device))
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if t.numel() != numel:
+        raise ValueError("%s must have %d elements, got %d" % (name, numel, t.numel()))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def _check_out(out, n2: int, device: torch.device):
+    if out is None:
+        return (torch.empty(n2, dtype=torch.float32, device=device),
+                torch.empty(n2, dtype=torch.int32, device=device))
+    M, idx = out
+    _check_tensor(M, "out M", torch.float32, n2, device)
+    _check_tensor(idx, "out idx", torch.int32, n2, device)
+    return M, idx
+
+
+def _check_workspace(ws, need: int, device: torch.device):
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or ws.device != device:
+        raise ValueError("workspace must be a CUDA tensor on %s" % device)
+    if not ws.is_contiguous() or ws.numel() * ws.element_size() < need:
+        raise ValueError("workspace must be contiguous and hold at least %d bytes" % need)
+    return ws
+
+
 def _check_square(W: torch.Tensor):
     if not isinstance(W, torch.Tensor) or not W.is_cuda:
         raise ValueError("W must be a CUDA (HIP) tensor")
@@ -136,6 +177,15 @@ def _check_square(W: torch.Tensor):
 
 def workspace_bytes(n: int) -> int:
     return int(lib().appd_forward_workspace_bytes(int(n)))
+
+
+def validate(W: torch.Tensor) -> int:
+    """Precondition flags of W (0: symmetric, NaN-free, zero diagonal); an or of
+    VALID_NAN, VALID_ASYM and VALID_DIAG.  Synchronises the current stream."""
+    n = _check_square(W)
+    flags = torch.empty(1, dtype=torch.int32, device=W.device)
+    _check(lib().appd_validate(_ptr(W), n, _ptr(flags), _stream(W.device)), "appd_validate")
+    return int(flags.item()) & 0xffffffff
 
 
 def _mode(mode: int, tree: str) -> int:
@@ -157,11 +207,8 @@ def forward(W: torch.Tensor, mode: int = MINIMAX, return_tree: bool = False, out
     n = _check_square(W)
     mode = _mode(mode, tree)
     dev = W.device
-    if out is None:
-        M = torch.empty((n, n), dtype=torch.float32, device=dev)
-        idx = torch.empty((n, n), dtype=torch.int32, device=dev)
-    else:
-        M, idx = out
+    M, idx = _check_out(out, n * n, dev)
+    M, idx = M.view(n, n), idx.view(n, n)
     order = parent = None
     if return_tree:
         order = torch.empty(n, dtype=torch.int32, device=dev)
@@ -169,6 +216,7 @@ def forward(W: torch.Tensor, mode: int = MINIMAX, return_tree: bool = False, out
     nb = workspace_bytes(n)
     if workspace is None:
         workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
+    _check_workspace(workspace, nb, dev)
     rc = lib().appd_forward_ex(_ptr(W), n, int(mode), _ptr(M), _ptr(idx), _ptr(order),
                                _ptr(parent), _ptr(workspace), workspace.numel(), _stream(dev))
     _check(rc, "appd_forward_ex")
@@ -198,6 +246,7 @@ def linkage(W: torch.Tensor, mode: int = MINIMAX, tree: str = "auto",
     Z = torch.empty((max(n - 1, 0), 4), dtype=torch.float64, device=W.device)
     if workspace is None:
         workspace = torch.empty(workspace_bytes(n), dtype=torch.uint8, device=W.device)
+    _check_workspace(workspace, workspace_bytes(n), W.device)
     _check(lib().appd_linkage(_ptr(W), n, int(mode), _ptr(Z) if n > 1 else None,
                               _ptr(workspace), workspace.numel(), _stream(W.device)),
            "appd_linkage")
@@ -207,6 +256,7 @@ def linkage(W: torch.Tensor, mode: int = MINIMAX, tree: str = "auto",
 def tree(W: torch.Tensor, workspace: torch.Tensor, mode: int = MINIMAX, tree: str = "auto"):
     """Phase 1 only: spanning tree and attachment order into `workspace`."""
     n = _check_square(W)
+    _check_workspace(workspace, workspace_bytes(n), W.device)
     _check(lib().appd_tree(_ptr(W), n, _mode(mode, tree), None, None, _ptr(workspace),
                            workspace.numel(), _stream(W.device)), "appd_tree")
 
@@ -214,6 +264,9 @@ def tree(W: torch.Tensor, workspace: torch.Tensor, mode: int = MINIMAX, tree: st
 def fill(n: int, workspace: torch.Tensor, M: torch.Tensor, idx: torch.Tensor,
          mode: int = MINIMAX):
     """Phase 2 only: M and idx from the tree `tree()` left in `workspace`."""
+    _check_workspace(workspace, workspace_bytes(n), workspace.device)
+    _check_tensor(M, "M", torch.float32, n * n, workspace.device)
+    _check_tensor(idx, "idx", torch.int32, n * n, workspace.device)
     _check(lib().appd_fill(int(n), int(mode), _ptr(workspace), workspace.numel(), _ptr(M),
                            _ptr(idx), _stream(M.device)), "appd_fill")
 
@@ -250,18 +303,30 @@ class Batch:
     def autotune(self, W: torch.Tensor, out=None) -> float:
         """Time the candidate schedules on this batch's W and keep the fastest;
         returns its milliseconds per forward.  Synchronises; not capturable."""
-        if W.dtype != torch.float32 or W.numel() != self.total_nn or not W.is_contiguous():
-            raise ValueError("W must be a contiguous float32 tensor of sum(n^2) elements")
-        if out is None:
-            M = torch.empty(self.total_nn, dtype=torch.float32, device=self.device)
-            idx = torch.empty(self.total_nn, dtype=torch.int32, device=self.device)
-        else:
-            M, idx = out
+        _check_tensor(W, "W", torch.float32, self.total_nn, self.device)
+        M, idx = _check_out(out, self.total_nn, self.device)
         ms = ctypes.c_float()
         _check(lib().appd_batch_autotune(_ptr(W), _ptr(M), _ptr(idx), ctypes.byref(self.plan),
                                          _ptr(self.ws), _stream(self.device), ctypes.byref(ms)),
                "appd_batch_autotune")
         return ms.value
+
+    def set_schedule(self, threads=None, rows=None, streams=None, split_count=None):
+        """Set the schedule by hand (Prim workgroup size and fill rows per item of
+        each class, streams, and how many of the largest class's biggest graphs
+        run on their own); rebuilds the device work tables.  Synchronises."""
+        p = self.plan
+        for c in range(BATCH_CLASSES):
+            if threads is not None:
+                p.class_threads[c] = int(threads[c] if hasattr(threads, "__len__") else threads)
+            if rows is not None:
+                p.class_rows[c] = int(rows[c] if hasattr(rows, "__len__") else rows)
+        if streams is not None:
+            p.streams = int(streams)
+        if split_count is not None:
+            p.split_count = int(split_count)
+        _check(lib().appd_batch_set_schedule(ctypes.byref(p), _ptr(self.ws), _stream(self.device)),
+               "appd_batch_set_schedule")
 
     def schedule(self) -> dict:
         """The plan's per-class schedule (classes n <= 64 .. 2048); split_count:
@@ -274,13 +339,8 @@ class Batch:
     def forward(self, W: torch.Tensor, mode: int = MINIMAX, return_parent: bool = False,
                 out=None):
         """Packed (M, idx[, parent]) of every graph of the batch."""
-        if W.dtype != torch.float32 or W.numel() != self.total_nn or not W.is_contiguous():
-            raise ValueError("W must be a contiguous float32 tensor of sum(n^2) elements")
-        if out is None:
-            M = torch.empty(self.total_nn, dtype=torch.float32, device=self.device)
-            idx = torch.empty(self.total_nn, dtype=torch.int32, device=self.device)
-        else:
-            M, idx = out
+        _check_tensor(W, "W", torch.float32, self.total_nn, self.device)
+        M, idx = _check_out(out, self.total_nn, self.device)
         parent = torch.empty(self.total_n, dtype=torch.int32, device=self.device) \
             if return_parent else None
         _check(lib().appd_forward_batched(_ptr(W), int(mode), _ptr(M), _ptr(idx), _ptr(parent),
@@ -290,23 +350,41 @@ class Batch:
 
     def pairwise(self, X: torch.Tensor, d: int, out: torch.Tensor = None) -> torch.Tensor:
         """Packed Euclidean W of the batch's point sets (X: total_n x d float32)."""
-        if X.dtype != torch.float32 or X.numel() != self.total_n * d or not X.is_contiguous():
-            raise ValueError("X must be a contiguous float32 tensor of total_n * d elements")
+        _check_tensor(X, "X", torch.float32, self.total_n * d, self.device)
         W = out if out is not None else torch.empty(self.total_nn, dtype=torch.float32,
                                                      device=self.device)
+        _check_tensor(W, "out W", torch.float32, self.total_nn, self.device)
         _check(lib().appd_pairwise_euclidean_batched(_ptr(X), int(d), _ptr(W),
                                                      ctypes.byref(self.plan), _ptr(self.ws),
                                                      _stream(self.device)),
                "appd_pairwise_euclidean_batched")
         return W
 
+    def _check_grad_args(self, G, idx, parent):
+        _check_tensor(G, "G", torch.float32, self.total_nn, self.device)
+        _check_tensor(idx, "idx", torch.int32, self.total_nn, self.device)
+        _check_tensor(parent, "parent", torch.int32, self.total_n, self.device)
+
     def backward_points(self, X, d, W, G, idx, parent) -> torch.Tensor:
+        _check_tensor(X, "X", torch.float32, self.total_n * d, self.device)
+        _check_tensor(W, "W", torch.float32, self.total_nn, self.device)
+        self._check_grad_args(G, idx, parent)
         dX = torch.empty(self.total_n * d, dtype=torch.float32, device=self.device)
         _check(lib().appd_backward_points_batched(_ptr(X), int(d), _ptr(W), _ptr(G), _ptr(idx),
                                                   _ptr(parent), _ptr(dX), ctypes.byref(self.plan),
                                                   _ptr(self.ws), _stream(self.device)),
                "appd_backward_points_batched")
         return dX
+
+    def backward_w(self, G, idx, parent) -> torch.Tensor:
+        """Packed dL/dW for L = sum G_ij M_ij: G_ij onto the upper-triangle entry
+        of each pair's bottleneck edge, per graph."""
+        self._check_grad_args(G, idx, parent)
+        dW = torch.empty(self.total_nn, dtype=torch.float32, device=self.device)
+        _check(lib().appd_backward_w_batched(_ptr(G), _ptr(idx), _ptr(parent), _ptr(dW),
+                                             ctypes.byref(self.plan), _ptr(self.ws),
+                                             _stream(self.device)), "appd_backward_w_batched")
+        return dW
 
 
 # ------------------------------------------------------------------ points, gradients
@@ -326,8 +404,21 @@ def pairwise_euclidean(X: torch.Tensor) -> torch.Tensor:
     return W
 
 
+def _check_single_grad(G, idx, parent, n, dev):
+    if n < 1 or n > GRAD_MAX_N:
+        raise ValueError("n must be in [1, %d] for the backward" % GRAD_MAX_N)
+    _check_tensor(G, "G", torch.float32, n * n, dev)
+    _check_tensor(idx, "idx", torch.int32, n * n, dev)
+    _check_tensor(parent, "parent", torch.int32, n, dev)
+
+
 def backward_points(X, W, G, idx, parent) -> torch.Tensor:
+    if X.dim() != 2:
+        raise ValueError("X must be n x d")
     n, d = X.shape
+    _check_tensor(X, "X", torch.float32, n * d, X.device)
+    _check_tensor(W, "W", torch.float32, n * n, X.device)
+    _check_single_grad(G, idx, parent, n, X.device)
     dX = torch.empty((n, d), dtype=torch.float32, device=X.device)
     ws = _grad_ws(n, X.device)
     _check(lib().appd_backward_points(_ptr(X), n, d, _ptr(W), _ptr(G), _ptr(idx), _ptr(parent),
@@ -338,6 +429,7 @@ def backward_points(X, W, G, idx, parent) -> torch.Tensor:
 
 def backward_w(G, idx, parent) -> torch.Tensor:
     n = G.shape[0]
+    _check_single_grad(G, idx, parent, n, G.device)
     dW = torch.empty((n, n), dtype=torch.float32, device=G.device)
     ws = _grad_ws(n, G.device)
     _check(lib().appd_backward_w(_ptr(G), _ptr(idx), _ptr(parent), n, _ptr(dW), _ptr(ws),

@@ -103,7 +103,34 @@ appd::BatchPlan device_plan(const appd_batch_plan* p, const Tables& t) {
     return bp;
 }
 
+// Stamp of what the device work tables (chunk_start) were built for: the rows
+// per fill item of every class and the cut of the largest class, which fix the
+// chunk numbering the fill kernels search.  FNV-1a over those fields.
+uint64_t tables_key_of(const appd_batch_plan* p) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](int64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    mix(p->num_graphs);
+    mix(p->total_n);
+    mix(p->total_nn);
+    for (int c = 0; c < appd::kBatchClasses; ++c) {
+        mix(p->class_first[c]);
+        mix(p->class_count[c]);
+        mix(p->class_rows[c]);
+        mix(p->class_chunks[c]);
+    }
+    mix(p->split_count);
+    mix(p->split_chunks);
+    return h;
+}
+
 bool schedule_ok(const appd_batch_plan* p) {
+    // the fields that index the device tables must be the ones they were built for
+    if (p->tables_key != tables_key_of(p)) return false;
     if (p->streams < 1 || p->streams > appd::kBatchClasses) return false;
     int top = -1;  // the largest class present
     for (int c = 0; c < appd::kBatchClasses; ++c)
@@ -121,13 +148,14 @@ bool schedule_ok(const appd_batch_plan* p) {
 }
 
 // Fill work items per class for the plan's rows per item; chunk_start[i] is the
-// first item of the i-th graph (n-descending order) within its class.  With
-// split, the largest class is cut after its graphs of n >= 0.84 n_max: a Prim
-// chain grows with n and a fill with n^2, and for sizes spread evenly on a log
-// scale over one class (n_max / 2, n_max] this cut gives the two parts about
-// the same Prim + fill time.
+// first item of the i-th graph (n-descending order) within its class.  split:
+// 0 no cut; -1 the largest class is cut after its graphs of n >= 0.84 n_max (a
+// Prim chain grows with n and a fill with n^2, and for sizes spread evenly on a
+// log scale over one class (n_max / 2, n_max] this cut gives the two parts
+// about the same Prim + fill time); h > 0 the cut after its first h graphs.
+// Sets class_chunks, split_count, split_chunks and the tables' stamp.
 void build_chunks(const int32_t* ns_host, const std::vector<int32_t>& perm, appd_batch_plan* p,
-                  std::vector<int32_t>& chunk_start, bool split) {
+                  std::vector<int32_t>& chunk_start, int split) {
     const int G = p->num_graphs;
     chunk_start.assign(G, 0);
     for (int c = 0; c < appd::kBatchClasses; ++c) p->class_chunks[c] = 0;
@@ -142,16 +170,21 @@ void build_chunks(const int32_t* ns_host, const std::vector<int32_t>& perm, appd
     int top = -1;
     for (int c = 0; c < appd::kBatchClasses; ++c)
         if (p->class_count[c]) top = c;
-    if (!split || top < 0) return;
-    const int first = p->class_first[top], count = p->class_count[top];
-    const int nmax = ns_host[perm[first]];
-    int h = 0;
-    while (h < count && 100 * (int64_t)ns_host[perm[first + h]] >= 84 * (int64_t)nmax) ++h;
-    if (h > 0 && h < count && chunk_start[first + h] > 0 &&
-        chunk_start[first + h] < p->class_chunks[top]) {
-        p->split_count = h;
-        p->split_chunks = chunk_start[first + h];
+    if (split != 0 && top >= 0) {
+        const int first = p->class_first[top], count = p->class_count[top];
+        const int nmax = ns_host[perm[first]];
+        int h = split;
+        if (split < 0) {
+            h = 0;
+            while (h < count && 100 * (int64_t)ns_host[perm[first + h]] >= 84 * (int64_t)nmax) ++h;
+        }
+        if (h > 0 && h < count && chunk_start[first + h] > 0 &&
+            chunk_start[first + h] < p->class_chunks[top]) {
+            p->split_count = h;
+            p->split_chunks = chunk_start[first + h];
+        }
     }
+    p->tables_key = tables_key_of(p);
 }
 
 // Default schedule: Prim workgroups of 64 threads up to n = 256, 256 threads
@@ -234,7 +267,7 @@ int appd_batch_prepare(const int32_t* ns_host, int num_graphs, void* ws, size_t 
     for (int c = 0; c < appd::kBatchClasses; ++c)
         if (p.class_first[c] < 0) p.class_first[c] = 0;
     default_schedule(&p);
-    build_chunks(ns_host, perm, &p, chunk_start, false);
+    build_chunks(ns_host, perm, &p, chunk_start, 0);
 
     // one host image of the table region, one synchronous copy
     std::vector<char> img(lay.table_bytes, 0);
@@ -300,7 +333,7 @@ int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan*
                     p.class_rows[c] = rows_opt[ri];
                 }
                 p.streams = streams_opt[si];
-                build_chunks(ns.data(), perm, &p, chunk_start, sp != 0);
+                build_chunks(ns.data(), perm, &p, chunk_start, sp ? -1 : 0);
                 if ((e = hipStreamSynchronize(s)) != hipSuccess ||
                     (e = hipMemcpy(t.chunk_start, chunk_start.data(), 4 * (size_t)G,
                                    hipMemcpyHostToDevice)) != hipSuccess)
@@ -324,7 +357,7 @@ int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan*
                     best = p;
                 }
             }
-    build_chunks(ns.data(), perm, &best, chunk_start, best.split_count > 0);
+    build_chunks(ns.data(), perm, &best, chunk_start, best.split_count);
     if ((e = hipMemcpy(t.chunk_start, chunk_start.data(), 4 * (size_t)G,
                        hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e);
@@ -332,6 +365,35 @@ int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan*
     (void)hipEventDestroy(e1);
     *plan = best;
     if (best_ms) *best_ms = best_t;
+    return ok();
+}
+
+int appd_batch_set_schedule(appd_batch_plan* plan, void* ws, void* stream) {
+    if (!plan_ok(plan, ws) || plan->streams < 1 || plan->streams > appd::kBatchClasses ||
+        plan->split_count < 0)
+        return fail(APPD_EINVAL);
+    for (int c = 0; c < appd::kBatchClasses; ++c) {
+        if (!plan->class_count[c]) continue;
+        if (plan->class_rows[c] < 1 || plan->class_rows[c] > APPD_BATCH_MAX_N ||
+            !appd::batch_threads_ok(c, plan->class_threads[c]))
+            return fail(APPD_EINVAL);
+    }
+    const int G = plan->num_graphs;
+    Tables t = carve(ws, G, plan->total_n);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int32_t> ns(G), perm(G), chunk_start;
+    if (hipStreamSynchronize(s) != hipSuccess ||
+        hipMemcpy(ns.data(), t.ns, 4 * (size_t)G, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(perm.data(), t.perm, 4 * (size_t)G, hipMemcpyDeviceToHost) != hipSuccess)
+        return hip_status(hipErrorUnknown);
+    appd_batch_plan p = *plan;
+    const int want = p.split_count;
+    build_chunks(ns.data(), perm, &p, chunk_start, want);
+    if (want > 0 && p.split_count != want) return fail(APPD_EINVAL);  // cut out of range
+    if (hipMemcpy(t.chunk_start, chunk_start.data(), 4 * (size_t)G, hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return hip_status(hipErrorUnknown);
+    *plan = p;
     return ok();
 }
 
@@ -446,7 +508,26 @@ int appd_backward_w(const float* G, const int32_t* idx, const int32_t* parent, i
     if (e == hipSuccess)
         e = appd::run_edge_grad(G, idx, t.offsets, t.noff, t.ns, parent, t.gchunk_start, 1,
                                 chunks, appd::kGradRows, n, t.gedge, s);
-    if (e == hipSuccess) e = appd::run_edge_to_w(t.gedge, parent, n, dW, s);
+    if (e == hipSuccess)
+        e = appd::run_edge_to_w(t.gedge, parent, t.offsets, t.noff, t.ns, t.vstart, 1,
+                                (n + appd::kChainThreads - 1) / appd::kChainThreads, dW, s);
+    return hip_status(e);
+}
+
+int appd_backward_w_batched(const float* G, const int32_t* idx, const int32_t* parent, float* dW,
+                            const appd_batch_plan* plan, void* ws, void* stream) {
+    if (!G || !idx || !parent || !dW || !plan_ok(plan, ws)) return fail(APPD_EINVAL);
+    Tables t = carve(ws, plan->num_graphs, plan->total_n);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = appd::run_zero(t.gedge, 4 * (size_t)plan->total_n, s);
+    if (e == hipSuccess) e = appd::run_zero(dW, 4 * (size_t)plan->total_nn, s);
+    if (e == hipSuccess)
+        e = appd::run_edge_grad(G, idx, t.offsets, t.noff, t.ns, parent, t.gchunk_start,
+                                plan->num_graphs, plan->grad_chunks, appd::kGradRows, plan->max_n,
+                                t.gedge, s);
+    if (e == hipSuccess)
+        e = appd::run_edge_to_w(t.gedge, parent, t.offsets, t.noff, t.ns, t.vstart,
+                                plan->num_graphs, plan->chain_blocks, dW, s);
     return hip_status(e);
 }
 

@@ -70,6 +70,9 @@ __global__ __launch_bounds__(kBatchFillThreads) void fill_batched_kernel(
     const int g = perm[gi];
     const int n = ns[g];
     const int chunk = b - chunk_start[gi];
+    // a work table that does not match this launch (never for a plan the host
+    // checks accepted) must not turn into writes outside the graph
+    if (chunk < 0 || (int64_t)chunk * rows >= n) return;
     const int64_t o = noff[g];
     const int32_t* pos = tree.pos + o;
     const uint64_t* ek = tree.ek + o;
@@ -172,6 +175,10 @@ struct SideStreams {
 };
 std::mutex g_side_mu;
 SideStreams g_side[64];
+// Held from the fork record to the last join wait of one batched forward: the
+// fork and join events are shared, so two host threads must not interleave
+// their record / wait sequences.
+std::mutex g_fork_mu;
 
 hipError_t side_streams(SideStreams** out) {
     int dev = 0;
@@ -208,7 +215,9 @@ static hipError_t run_batched_t(const float* W, const int64_t* offsets, const in
     st[0] = s;
     SideStreams* ss = nullptr;
     hipError_t e;
+    std::unique_lock<std::mutex> fork_lock(g_fork_mu, std::defer_lock);
     if (nstreams > 1) {
+        fork_lock.lock();
         if ((e = side_streams(&ss)) != hipSuccess) return e;
         if ((e = hipEventRecord(ss->fork, s)) != hipSuccess) return e;
         for (int k = 1; k < nstreams; ++k) {

@@ -269,21 +269,30 @@ hipError_t run_single_table(int n, int32_t* ns, int64_t* offsets, int64_t* noff,
     return hipGetLastError();
 }
 
-// dW[min(c,p)*n + max(c,p)] = gedge[c] for each tree edge (c, parent c).
-__global__ void edge_to_w_kernel(const float* __restrict__ gedge, const int32_t* __restrict__ parent,
-                                 int n, float* __restrict__ dW) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// dW[min(c,p)*n + max(c,p)] = gedge[c] for each tree edge (c, parent c) of
+// every graph (vertex blocks located through vstart, as in the chain kernel).
+__global__ __launch_bounds__(256) void edge_to_w_kernel(
+    const float* __restrict__ gedge, const int32_t* __restrict__ parent,
+    const int64_t* __restrict__ offsets, const int64_t* __restrict__ noff,
+    const int32_t* __restrict__ ns, const int32_t* __restrict__ vstart, int num_graphs,
+    float* __restrict__ dW) {
+    const int g = find_item(vstart, num_graphs, blockIdx.x);
+    const int n = ns[g];
+    const int c = (blockIdx.x - vstart[g]) * blockDim.x + threadIdx.x;
     if (c >= n) return;
-    const int p = parent[c];
-    if (p < 0) return;
+    const int p = parent[noff[g] + c];
+    if (p < 0 || p >= n) return;
     const int u = c < p ? c : p, v = c < p ? p : c;
-    dW[(size_t)u * n + v] = gedge[c];
+    dW[offsets[g] + (size_t)u * n + v] = gedge[noff[g] + c];
 }
 
-hipError_t run_edge_to_w(const float* gedge, const int32_t* parent, int n, float* dW,
-                         hipStream_t s) {
+hipError_t run_edge_to_w(const float* gedge, const int32_t* parent, const int64_t* offsets,
+                         const int64_t* noff, const int32_t* ns, const int32_t* vstart,
+                         int num_graphs, int total_vblocks, float* dW, hipStream_t s) {
+    if (total_vblocks == 0) return hipSuccess;
     APPD_LAUNCH("edge_to_w_kernel", s,
-        edge_to_w_kernel<<<(n + 255) / 256, 256, 0, s>>>(gedge, parent, n, dW));
+        edge_to_w_kernel<<<total_vblocks, 256, 0, s>>>(gedge, parent, offsets, noff, ns, vstart,
+            num_graphs, dW));
     return hipGetLastError();
 }
 

@@ -106,8 +106,9 @@ hipError_t run_scale_offsets(const int64_t* noff, int num_graphs, int d, int64_t
 hipError_t run_single_table(int n, int32_t* ns, int64_t* offsets, int64_t* noff,
                             int32_t* tile_start, int32_t* gchunk_start, int32_t* vstart,
                             hipStream_t s);
-hipError_t run_edge_to_w(const float* gedge, const int32_t* parent, int n, float* dW,
-                         hipStream_t s);
+hipError_t run_edge_to_w(const float* gedge, const int32_t* parent, const int64_t* offsets,
+                         const int64_t* noff, const int32_t* ns, const int32_t* vstart,
+                         int num_graphs, int total_vblocks, float* dW, hipStream_t s);
 int pairwise_tile();
 int pairwise_max_d();
 constexpr int kGradRows = 32;

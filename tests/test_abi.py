@@ -86,16 +86,17 @@ def test_batch_plan_struct_layout_matches_header(tmp_path):
     import subprocess
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "appd.h"\n'
-                   'int main(){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(appd_batch_plan),'
+                   'int main(){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(appd_batch_plan),'
                    'offsetof(appd_batch_plan, class_first), offsetof(appd_batch_plan, class_threads),'
                    'offsetof(appd_batch_plan, streams), offsetof(appd_batch_plan, pair_tiles),'
-                   'offsetof(appd_batch_plan, ws_bytes));return 0;}\n')
+                   'offsetof(appd_batch_plan, ws_bytes), offsetof(appd_batch_plan, tables_key));'
+                   'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     P = appd.BatchPlan
     assert got == [ctypes.sizeof(P), P.class_first.offset, P.class_threads.offset,
-                   P.streams.offset, P.pair_tiles.offset, P.ws_bytes.offset]
+                   P.streams.offset, P.pair_tiles.offset, P.ws_bytes.offset, P.tables_key.offset]
 
 
 def test_batch_workspace_and_bad_sizes():
@@ -126,3 +127,48 @@ def test_grad_calls_reject_bad_arguments():
     assert L.appd_pairwise_euclidean(p, 10, 3, p, p, 1, None) == appd.APPD_EINVAL
     assert L.appd_backward_points(p, 32769, 3, p, p, p, p, p, p, 1 << 30, None) == appd.APPD_EINVAL
     assert L.appd_backward_w(p, p, None, 10, p, p, 1 << 20, None) == appd.APPD_EINVAL
+
+
+def test_batched_plan_out_of_step_with_its_tables_is_rejected():
+    """A plan whose rows per item or cut were edited after the device work
+    tables were built (the stamp no longer matches) is rejected before any
+    launch, like one that was never prepared."""
+    L = appd.lib()
+    P = ctypes.c_void_p
+    plan = appd.BatchPlan()
+    plan.num_graphs = 3
+    plan.total_n = 48
+    plan.total_nn = 768
+    plan.ws_bytes = 1 << 20
+    plan.streams = 2
+    plan.class_count[0] = 3
+    plan.class_rows[0] = 16
+    plan.class_threads[0] = 64
+    plan.class_chunks[0] = 3
+    plan.split_count = 1
+    plan.split_chunks = 2  # inconsistent with one 16-row item per graph
+    plan.tables_key = 12345
+    assert L.appd_forward_batched(P(256), 0, P(256), P(256), None, ctypes.byref(plan), P(256),
+                                  None) == appd.APPD_EINVAL
+    assert L.appd_get_last_error() == appd.APPD_EINVAL
+    assert L.appd_batch_autotune(P(256), P(256), P(256), ctypes.byref(plan), P(256), None,
+                                 None) == appd.APPD_EINVAL
+
+
+def test_validate_rejects_bad_arguments():
+    L = appd.lib()
+    P = ctypes.c_void_p
+    assert L.appd_validate(None, 4, P(256), None) == appd.APPD_EINVAL
+    assert L.appd_validate(P(256), 4, None, None) == appd.APPD_EINVAL
+    assert L.appd_validate(P(256), 0, P(256), None) == appd.APPD_EINVAL
+    assert L.appd_validate(P(256), 46341, P(256), None) == appd.APPD_EINVAL
+
+
+def test_backward_w_batched_rejects_bad_arguments():
+    L = appd.lib()
+    P = ctypes.c_void_p
+    plan = appd.BatchPlan()
+    assert L.appd_backward_w_batched(P(256), P(256), P(256), P(256), ctypes.byref(plan), P(256),
+                                     None) == appd.APPD_EINVAL
+    assert L.appd_backward_w_batched(None, P(256), P(256), P(256), ctypes.byref(plan), P(256),
+                                     None) == appd.APPD_EINVAL

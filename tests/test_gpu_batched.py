@@ -134,17 +134,10 @@ def test_batched_graph_capture_replays():
         _ = (M0 * 2).sum().item()  # eager work between replays
 
 
-def set_schedule(b, threads, rows, streams):
-    for c in range(appd.BATCH_CLASSES):
-        b.plan.class_threads[c] = threads[c]
-        b.plan.class_rows[c] = rows
-    b.plan.streams = streams
-
-
 def test_batched_schedules_identical():
     """Every Prim workgroup size, rows per fill item and class concurrency gives
     the same bits as the default schedule.  (Rows per item change the fill work
-    tables, so each schedule here goes through a fresh, re-prepared batch.)"""
+    tables, which the schedule call rebuilds.)"""
     say("case batched schedules")
     Ws = mixed_graphs(6)
     flat, offsets, ns = workloads.pack(Ws)
@@ -157,12 +150,16 @@ def test_batched_schedules_identical():
     narrow = [64, 64, 64, 256, 256, 256]
     wide = [64, 128, 256, 512, 512, 1024]
     mid = [64, 128, 128, 128, 512, 512]
-    for threads, streams in [(narrow, 1), (wide, 3), (mid, 6), (wide, 2)]:
-        b = appd.Batch(ns, DEV)
-        set_schedule(b, threads, 16, streams)  # rows unchanged: tables still valid
+    b = appd.Batch(ns, DEV)
+    for threads, rows, streams in [(narrow, 16, 1), (wide, 32, 3), (mid, 7, 6), (wide, 64, 2)]:
+        b.set_schedule(threads=threads, rows=rows, streams=streams, split_count=0)
         M, I = b.forward(Wd)
         torch.cuda.synchronize()
-        assert torch.equal(M, M0) and torch.equal(I, I0), (threads, streams)
+        assert torch.equal(M, M0) and torch.equal(I, I0), (threads, rows, streams)
+    # a field edited behind the work tables' back is rejected before any launch
+    b.plan.class_rows[0] += 1
+    with pytest.raises(appd.APPDError):
+        b.forward(Wd)
 
 
 def test_batched_split_largest_class():
@@ -183,19 +180,20 @@ def test_batched_split_largest_class():
     assert len(members) >= 2, members
     for h, streams in [(1, 2), (len(members) // 2, 3), (len(members) - 1, 5)]:
         b = appd.Batch(ns, DEV)
+        b.set_schedule(streams=streams, split_count=int(h))
         rows = b.plan.class_rows[top]
-        b.plan.streams = streams
-        b.plan.split_count = int(h)
-        b.plan.split_chunks = int(sum((int(n) + rows - 1) // rows for n in members[:h]))
+        assert b.plan.split_count == h
+        assert b.plan.split_chunks == sum((int(n) + rows - 1) // rows for n in members[:h])
         M, I = b.forward(Wd)
         torch.cuda.synchronize()
         assert torch.equal(M, M0) and torch.equal(I, I0), (h, streams)
+        # a cut edited by hand no longer matches the work tables: rejected
+        b.plan.split_chunks += 1
+        with pytest.raises(appd.APPDError):
+            b.forward(Wd)
     b = appd.Batch(ns, DEV)
-    b.plan.streams = 3
-    b.plan.split_count = len(members)
-    b.plan.split_chunks = 1
     with pytest.raises(appd.APPDError):
-        b.forward(Wd)
+        b.set_schedule(streams=3, split_count=len(members))
 
 
 def test_batched_autotune_bit_exact():
@@ -226,7 +224,7 @@ def test_batched_streams_graph_capture_replays():
     Ws = mixed_graphs(8)
     flat, offsets, ns = workloads.pack(Ws)
     b = appd.Batch(ns, DEV)
-    set_schedule(b, [64, 128, 256, 512, 512, 1024], 16, 4)
+    b.set_schedule(threads=[64, 128, 256, 512, 512, 1024], rows=16, streams=4)
     Wd = torch.from_numpy(flat).to(DEV)
     M0, I0 = b.forward(Wd)
     torch.cuda.synchronize()
@@ -332,6 +330,29 @@ def test_backward_w_single():
     off = io >= 0
     np.add.at(ref, io[off], G.astype(np.float64)[off])
     grad_close(Wd.grad.cpu().numpy().ravel().astype(np.float64), ref)
+
+
+def test_backward_w_batched():
+    """Packed dL/dW of a batch of weight matrices: per graph, G_ij onto the
+    upper-triangle entry of each pair's bottleneck edge (the oracle's idx)."""
+    say("case backward W batched")
+    Ws = mixed_graphs(9)[:16]
+    flat, offsets, ns = workloads.pack(Ws)
+    b = appd.Batch(ns, DEV)
+    M, idx, parent = b.forward(torch.from_numpy(flat).to(DEV), return_parent=True)
+    rng = np.random.default_rng(10)
+    G = rng.standard_normal(flat.size).astype(np.float32)
+    dW = b.backward_w(torch.from_numpy(G).to(DEV), idx, parent)
+    torch.cuda.synchronize()
+    dWh = dW.cpu().numpy()
+    for g, W in enumerate(Ws):
+        n = W.shape[0]
+        o = int(offsets[g])
+        _, io = oracle.appd(W)
+        ref = np.zeros(n * n)
+        off = io >= 0
+        np.add.at(ref, io[off], G[o:o + n * n].reshape(n, n).astype(np.float64)[off])
+        grad_close(dWh[o:o + n * n].astype(np.float64), ref)
 
 
 @pytest.mark.timeout(600)

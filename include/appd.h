@@ -108,6 +108,21 @@ int appd_forward_ws(const float* W, int n, float* M, int32_t* idx, void* ws, siz
                     void* stream);
 
 /*
+ * As appd_forward_ws, with no allocation at all and no workspace argument: for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc).  The workspace is a
+ * library-owned device array of APPD_NOALLOC_SCRATCH_BYTES per GPU, held by
+ * each GPU the library runs on until the process ends; every n in
+ * 1..APPD_MAX_N fits it (APPD_EINVAL otherwise, as for a null pointer).  Calls
+ * on one GPU share that array: calls that overlap on one GPU (different
+ * streams, or host threads without ordering between them) race, so order them.
+ * The device address of the array is looked up on the first call on each
+ * device (APPD_EHIP if that fails).  Results equal appd_forward_ws's.
+ */
+#define APPD_NOALLOC_SCRATCH_BYTES (12u << 20)
+int appd_forward_noalloc(const float* W, int n, float* M, int32_t* idx, void* stream);
+
+/*
  * Extended single-graph forward.
  *   mode      APPD_MINIMAX or APPD_WIDEST, optionally or-ed with one
  *             APPD_TREE_* flag.

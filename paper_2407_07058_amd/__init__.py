@@ -44,6 +44,7 @@ SIGNATURES = {
     "appd_forward": ([_P, _I, _P, _P, _P], _I),
     "appd_forward_ws": ([_P, _I, _P, _P, _P, _SZ, _P], _I),
     "appd_forward_ex": ([_P, _I, _I, _P, _P, _P, _P, _P, _SZ, _P], _I),
+    "appd_forward_noalloc": ([_P, _I, _P, _P, _P], _I),
     "appd_tree": ([_P, _I, _I, _P, _P, _P, _SZ, _P], _I),
     "appd_fill": ([_I, _I, _P, _SZ, _P, _P, _P], _I),
     "appd_linkage": ([_P, _I, _I, _P, _P, _SZ, _P], _I),

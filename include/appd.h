@@ -317,6 +317,24 @@ int appd_timer_start(const char* kernel, int capacity);
 int appd_timer_read(const char* kernel, int* launches, double* total_ms, int* overflow);
 int appd_timer_names(const char** names, int capacity);
 
+/* ------------------------------------------------------------------ reference points
+ * Measurement aids, not part of the method: the figures the kernels are
+ * compared with, taken on the same GPU.
+ * appd_membench_copy: dst = src, `bytes` (a multiple of 16, both 16-byte
+ *   aligned) as a plain streaming copy (non-temporal 16-byte loads and stores,
+ *   every CU busy).
+ * appd_membench_write: `bytes` of dst set to the 32-bit `value`, store only.
+ * appd_membench_chase: one lane follows p = next[p] from `start` for `steps`
+ *   dependent loads (indices >= length are taken as 0, so any table stays in
+ *   bounds) and writes the final p to *out: the time per step is the latency of
+ *   a chain of dependent loads.
+ * All device pointers, stream-ordered; APPD_EINVAL for null or misaligned
+ * arguments. */
+int appd_membench_copy(const void* src, void* dst, size_t bytes, void* stream);
+int appd_membench_write(void* dst, size_t bytes, uint32_t value, void* stream);
+int appd_membench_chase(const uint32_t* next, uint32_t length, uint32_t start, int steps,
+                        uint32_t* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,16 +23,44 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+_FLAGS = ["-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-Wall"]
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no FMA contraction) into liboracle.so."""
+    """Compile the oracle with gcc (-O3, no FMA contraction) into liboracle.so.
+    Portable code: the library also runs on hosts other than the build host."""
     if not force and os.path.exists(_LIB):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"]
-    subprocess.run(cmd, check=True)
+    subprocess.run(["gcc", "-O3", *_FLAGS, "-o", tmp, _SRC, "-lm"], check=True)
     os.replace(tmp, _LIB)
     return _LIB
+
+
+_SIGS = [
+    ("oracle_appd_alg4", ["P", "I64", "P", "P"]),
+    ("oracle_appd_alg4_f64", ["P", "I64", "P", "P"]),
+    ("oracle_appd_widest", ["P", "I64", "P", "P"]),
+    ("oracle_appd_alg4_rows", ["P", "I64", "P", "I64", "I", "P", "P"]),
+    ("oracle_mst_prim", ["P", "I64", "I", "P", "P", "P", "P"]),
+    ("oracle_linkage", ["P", "I64", "I", "P"]),
+    ("oracle_appd_fw", ["P", "I64", "I", "P", "P"]),
+    ("oracle_pairwise_euclidean_f32", ["P", "I64", "I64", "P"]),
+    ("oracle_pairwise_euclidean_f64", ["P", "I64", "I64", "P"]),
+    ("oracle_grad_points", ["P", "I64", "I64", "P", "P", "P", "P"]),
+]
+
+
+def _bind(path):
+    lib = ctypes.CDLL(path)
+    T = {"P": ctypes.c_void_p, "I64": ctypes.c_int64, "I": ctypes.c_int}
+    for name, args in _SIGS:
+        f = getattr(lib, name)
+        f.argtypes = [T[a] for a in args]
+        f.restype = ctypes.c_int
+    lib.oracle_loss_f64.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+    lib.oracle_loss_f64.restype = ctypes.c_double
+    return lib
 
 
 def _load():
@@ -41,28 +69,26 @@ def _load():
         return _lib
     if not os.path.exists(_LIB):
         build()
-    lib = ctypes.CDLL(_LIB)
-    P = ctypes.c_void_p
-    I64 = ctypes.c_int64
-    for name, args in [
-        ("oracle_appd_alg4", [P, I64, P, P]),
-        ("oracle_appd_alg4_f64", [P, I64, P, P]),
-        ("oracle_appd_widest", [P, I64, P, P]),
-        ("oracle_appd_alg4_rows", [P, I64, P, I64, ctypes.c_int, P, P]),
-        ("oracle_mst_prim", [P, I64, ctypes.c_int, P, P, P, P]),
-        ("oracle_linkage", [P, I64, ctypes.c_int, P]),
-        ("oracle_appd_fw", [P, I64, ctypes.c_int, P, P]),
-        ("oracle_pairwise_euclidean_f32", [P, I64, I64, P]),
-        ("oracle_pairwise_euclidean_f64", [P, I64, I64, P]),
-        ("oracle_grad_points", [P, I64, I64, P, P, P, P]),
-    ]:
-        f = getattr(lib, name)
-        f.argtypes = args
-        f.restype = ctypes.c_int
-    lib.oracle_loss_f64.argtypes = [P, P, I64]
-    lib.oracle_loss_f64.restype = ctypes.c_double
-    _lib = lib
-    return lib
+    _lib = _bind(_LIB)
+    return _lib
+
+
+_native = None
+
+
+def native_build():
+    """The oracle compiled for this host with -O3 -march=native (the CPU
+    timing reference), built at run time into a temporary directory, since a
+    library tuned for one host's instruction set must not travel to another."""
+    global _native
+    if _native is None:
+        import tempfile
+        d = tempfile.mkdtemp(prefix="appd_oracle_")
+        path = os.path.join(d, "liboracle_native.so")
+        subprocess.run(["gcc", "-O3", "-march=native", *_FLAGS, "-o", path, _SRC, "-lm"],
+                       check=True)
+        _native = _bind(path)
+    return _native
 
 
 def _p(a: np.ndarray):
@@ -81,13 +107,20 @@ def _sq(W, dtype):
     return W
 
 
-def appd(W: np.ndarray):
-    """Algorithm 4 on a float32 weight matrix -> (M float32, idx int32)."""
+def appd(W: np.ndarray, lib=None, out=None):
+    """Algorithm 4 on a float32 weight matrix -> (M float32, idx int32).
+    lib: a library from native_build() instead of the portable one; out:
+    optional (M, idx) arrays to write into."""
     W = _sq(W, np.float32)
     n = W.shape[0]
-    M = np.empty((n, n), np.float32)
-    idx = np.empty((n, n), np.int32)
-    _chk(_load().oracle_appd_alg4(_p(W), n, _p(M), _p(idx)), "oracle_appd_alg4")
+    if out is None:
+        M = np.empty((n, n), np.float32)
+        idx = np.empty((n, n), np.int32)
+    else:
+        M, idx = out
+        assert M.shape == (n, n) and M.dtype == np.float32 and M.flags.c_contiguous
+        assert idx.shape == (n, n) and idx.dtype == np.int32 and idx.flags.c_contiguous
+    _chk((lib or _load()).oracle_appd_alg4(_p(W), n, _p(M), _p(idx)), "oracle_appd_alg4")
     return M, idx
 
 
@@ -156,11 +189,12 @@ def appd_fw(W: np.ndarray, widest: bool = False):
     return M, idx
 
 
-def pairwise_euclidean_f32(X: np.ndarray) -> np.ndarray:
+def pairwise_euclidean_f32(X: np.ndarray, lib=None) -> np.ndarray:
     X = np.ascontiguousarray(X, dtype=np.float32)
     n, d = X.shape
     W = np.empty((n, n), np.float32)
-    _chk(_load().oracle_pairwise_euclidean_f32(_p(X), n, d, _p(W)), "pairwise_euclidean_f32")
+    _chk((lib or _load()).oracle_pairwise_euclidean_f32(_p(X), n, d, _p(W)),
+         "pairwise_euclidean_f32")
     return W
 
 
@@ -172,7 +206,8 @@ def pairwise_euclidean_f64(X: np.ndarray) -> np.ndarray:
     return W
 
 
-def grad_points(X: np.ndarray, G: np.ndarray, idx: np.ndarray, with_edges: bool = False):
+def grad_points(X: np.ndarray, G: np.ndarray, idx: np.ndarray, with_edges: bool = False,
+                lib=None):
     """dL/dX (float64) of L = sum_{i!=j} G_ij M_ij through the bottleneck edges idx."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     G = np.ascontiguousarray(G, dtype=np.float64)
@@ -180,7 +215,7 @@ def grad_points(X: np.ndarray, G: np.ndarray, idx: np.ndarray, with_edges: bool 
     n, d = X.shape
     dX = np.empty((n, d), np.float64)
     ge = np.empty((n, n), np.float64) if with_edges else None
-    _chk(_load().oracle_grad_points(_p(X), n, d, _p(G), _p(idx), _p(dX),
+    _chk((lib or _load()).oracle_grad_points(_p(X), n, d, _p(G), _p(idx), _p(dX),
                                     _p(ge) if with_edges else None), "oracle_grad_points")
     return (dX, ge) if with_edges else dX
 

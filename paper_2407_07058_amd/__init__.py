@@ -61,6 +61,9 @@ SIGNATURES = {
     "appd_backward_points": ([_P, _I, _I, _P, _P, _P, _P, _P, _P, _SZ, _P], _I),
     "appd_backward_w": ([_P, _P, _P, _I, _P, _P, _SZ, _P], _I),
     "appd_backward_w_batched": ([_P, _P, _P, _P, _P, _P, _P], _I),
+    "appd_membench_copy": ([_P, _P, _SZ, _P], _I),
+    "appd_membench_write": ([_P, _SZ, ctypes.c_uint32, _P], _I),
+    "appd_membench_chase": ([_P, ctypes.c_uint32, ctypes.c_uint32, _I, _P, _P], _I),
     "appd_timer_start": ([ctypes.c_char_p, _I], _I),
     "appd_timer_read": ([ctypes.c_char_p, _P, _P, _P], _I),
     "appd_timer_names": ([_P, _I], _I),

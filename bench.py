@@ -358,8 +358,10 @@ def bench_batched(appd, torch, steps, lean=False):
     t1.record()
     torch.cuda.synchronize()
     ms_b = elapsed(t0, t1) / steps
+    tstats = b.tree_stats()
     if lean:  # profiling: the replays alone
-        return {"batched_ms": ms_b, "entries": entries, "schedule": sched, "lean": True}
+        return {"batched_ms": ms_b, "entries": entries, "schedule": sched, "lean": True,
+                "tree_stats": tstats}
     Mb = M.clone()
     Ib = I.clone()
 
@@ -403,7 +405,7 @@ def bench_batched(appd, torch, steps, lean=False):
             "schedule": sched, "autotune_best_ms_per_forward": tune_ms,
             "autotune_wall_s": tune_wall,
             "loop": "%d appd_forward_ws calls on one stream" % len(ns),
-            "outputs_identical": same, "cpu_oracle": cpu}
+            "outputs_identical": same, "tree_stats": tstats, "cpu_oracle": cpu}
 
 
 def oracle_appd_native(W):
@@ -465,8 +467,10 @@ def bench_fwd_bwd(appd, torch, steps, lean=False):
     t1.record()
     torch.cuda.synchronize()
     ms_b = elapsed(t0, t1) / steps
+    tstats = b.tree_stats()
     if lean:  # profiling: the batched steps alone
-        return {"batched_ms": ms_b, "entries": entries, "schedule": b.schedule(), "lean": True}
+        return {"batched_ms": ms_b, "entries": entries, "schedule": b.schedule(), "lean": True,
+                "tree_stats": tstats}
 
     L = appd.lib()
     stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
@@ -528,7 +532,7 @@ def bench_fwd_bwd(appd, torch, steps, lean=False):
             "loop": "%d x (appd_pairwise_euclidean, appd_forward_ex, appd_backward_points)"
                     % len(ns),
             "schedule": b.schedule(),
-            "dX_rel_diff_loop_vs_batched": err, "cpu_oracle": cpu}
+            "dX_rel_diff_loop_vs_batched": err, "tree_stats": tstats, "cpu_oracle": cpu}
 
 
 LEGS = ("single", "large", "batched", "fwd_bwd", "reference")

@@ -185,8 +185,9 @@ int appd_linkage(const float* W, int n, int mode, double* Z, void* ws, size_t ws
  *
  * Graphs are grouped into size classes (n <= 64, 128, 256, 512, 1024, 2048)
  * and listed by decreasing n, so the longest Prim chains start first.  Each
- * class runs Prim's algorithm (one workgroup per graph, class_threads[c]
- * threads) and then the fill (work items of class_rows[c] rows); up to
+ * class finds its spanning trees (class_tree[c]: Prim's algorithm with one
+ * workgroup of class_threads[c] threads per graph, or Boruvka rounds over
+ * candidate lists) and then runs the fill (work items of class_rows[c] rows); up to
  * `streams` classes proceed concurrently on library streams forked from and
  * joined back into `stream` (the largest class alone on `stream`, the others
  * in turn on the library streams; with split_count, the largest class's
@@ -227,7 +228,18 @@ typedef struct {
     int split_chunks; /* fill work items of those graphs (set with split_count) */
     uint64_t tables_key; /* stamp of the rows per item and cut the device work tables were
                             built for; a plan whose fields no longer match it is rejected */
+    int class_tree[APPD_BATCH_CLASSES];     /* how the class's trees are found:
+                                               APPD_BATCH_TREE_PRIM or APPD_BATCH_TREE_BORUVKA */
+    int class_vertices[APPD_BATCH_CLASSES]; /* sum of n over the class's graphs */
 } appd_batch_plan;
+
+/* class_tree values.  Prim: one workgroup per graph runs Prim's algorithm
+ * (n - 1 dependent steps).  Boruvka: a pass over the class's rows keeps each
+ * row's 16 smallest entries, then one workgroup per graph runs Boruvka rounds
+ * on them and rebuilds Prim's attachment order from the tree (refresh passes,
+ * then Prim, for a graph the lists cannot finish).  Identical outputs. */
+#define APPD_BATCH_TREE_PRIM 0
+#define APPD_BATCH_TREE_BORUVKA 1
 
 /* Workspace bytes for a batch with these sizes (0 on invalid input). */
 size_t appd_batch_workspace_bytes(const int32_t* ns_host, int num_graphs);
@@ -250,6 +262,14 @@ int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan*
  * split_chunks, tables_key) set.  Checks the schedule (APPD_EINVAL if it is not
  * one the kernels support); synchronises and is not capturable. */
 int appd_batch_set_schedule(appd_batch_plan* plan, void* ws, void* stream);
+
+/* How the last batched forward found each graph's tree (for measurement), by
+ * graph id into stats (num_graphs int32, host): -1 Prim's algorithm; else
+ * rounds | passes << 8 | fallback << 16 of the Boruvka path (passes over the
+ * graph's W; fallback 1 when Prim's algorithm had to finish it).  Synchronises
+ * `stream`. */
+int appd_batch_tree_stats(const appd_batch_plan* plan, const void* ws, int32_t* stats,
+                          void* stream);
 
 /* Batched forward (Algorithm 4 per graph).  parent: nullable, total_n int32. */
 int appd_forward_batched(const float* W, int mode, float* M, int32_t* idx, int32_t* parent,

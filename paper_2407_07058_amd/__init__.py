@@ -53,6 +53,7 @@ SIGNATURES = {
     "appd_batch_prepare": ([_P, _I, _P, _SZ, _P, _P], _I),
     "appd_forward_batched": ([_P, _I, _P, _P, _P, _P, _P, _P], _I),
     "appd_batch_set_schedule": ([_P, _P, _P], _I),
+    "appd_batch_tree_stats": ([_P, _P, _P, _P], _I),
     "appd_batch_autotune": ([_P, _P, _P, _P, _P, _P, _P], _I),
     "appd_pairwise_euclidean_batched": ([_P, _I, _P, _P, _P, _P], _I),
     "appd_backward_points_batched": ([_P, _I, _P, _P, _P, _P, _P, _P, _P, _P], _I),
@@ -74,6 +75,7 @@ VALID_ASYM = 0x2
 VALID_DIAG = 0x4
 
 BATCH_MAX_N = 2048
+BATCH_TREES = {"prim": 0, "boruvka": 1}
 BATCH_CLASSES = 6
 MAX_DIM = 64
 GRAD_MAX_N = 32768
@@ -91,7 +93,9 @@ class BatchPlan(ctypes.Structure):
                 ("streams", ctypes.c_int), ("pair_tiles", ctypes.c_int),
                 ("grad_chunks", ctypes.c_int), ("chain_blocks", ctypes.c_int),
                 ("ws_bytes", ctypes.c_size_t), ("split_count", ctypes.c_int),
-                ("split_chunks", ctypes.c_int), ("tables_key", ctypes.c_uint64)]
+                ("split_chunks", ctypes.c_int), ("tables_key", ctypes.c_uint64),
+                ("class_tree", ctypes.c_int * BATCH_CLASSES),
+                ("class_vertices", ctypes.c_int * BATCH_CLASSES)]
 
 _lib = None
 
@@ -315,7 +319,7 @@ class Batch:
                "appd_batch_autotune")
         return ms.value
 
-    def set_schedule(self, threads=None, rows=None, streams=None, split_count=None):
+    def set_schedule(self, threads=None, rows=None, streams=None, split_count=None, trees=None):
         """Set the schedule by hand (Prim workgroup size and fill rows per item of
         each class, streams, and how many of the largest class's biggest graphs
         run on their own); rebuilds the device work tables.  Synchronises."""
@@ -325,6 +329,9 @@ class Batch:
                 p.class_threads[c] = int(threads[c] if hasattr(threads, "__len__") else threads)
             if rows is not None:
                 p.class_rows[c] = int(rows[c] if hasattr(rows, "__len__") else rows)
+            if trees is not None:  # "prim" / "boruvka" per class, or one for all
+                tr = trees[c] if isinstance(trees, (list, tuple)) else trees
+                p.class_tree[c] = BATCH_TREES[tr]
         if streams is not None:
             p.streams = int(streams)
         if split_count is not None:
@@ -332,13 +339,30 @@ class Batch:
         _check(lib().appd_batch_set_schedule(ctypes.byref(p), _ptr(self.ws), _stream(self.device)),
                "appd_batch_set_schedule")
 
+    def tree_stats(self) -> dict:
+        """How the last forward found each graph's tree: counts of graphs by
+        Prim / Boruvka, the passes over W and rounds they took, fallbacks."""
+        st = np.empty(self.G, np.int32)
+        _check(lib().appd_batch_tree_stats(ctypes.byref(self.plan), _ptr(self.ws),
+                                           st.ctypes.data_as(_P), _stream(self.device)),
+               "appd_batch_tree_stats")
+        b = st[st >= 0]
+        return {"prim": int((st < 0).sum()), "boruvka": int(len(b)),
+                "fallback": int(((b >> 16) & 1).sum()),
+                "passes_max": int(((b >> 8) & 0xff).max()) if len(b) else 0,
+                "multi_pass": int((((b >> 8) & 0xff) > 1).sum()),
+                "rounds_max": int((b & 0xff).max()) if len(b) else 0,
+                "rounds_mean": float((b & 0xff).mean()) if len(b) else 0.0}
+
     def schedule(self) -> dict:
         """The plan's per-class schedule (classes n <= 64 .. 2048); split_count:
         graphs of the largest class launched on their own (0: not cut)."""
         p = self.plan
+        names = {v: k for k, v in BATCH_TREES.items()}
         return {"class_count": list(p.class_count), "class_threads": list(p.class_threads),
                 "class_rows": list(p.class_rows), "streams": p.streams,
-                "split_count": p.split_count}
+                "split_count": p.split_count,
+                "class_tree": [names.get(x, x) for x in p.class_tree]}
 
     def forward(self, W: torch.Tensor, mode: int = MINIMAX, return_parent: bool = False,
                 out=None):

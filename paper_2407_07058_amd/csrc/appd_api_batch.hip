@@ -31,12 +31,16 @@ struct Tables {
     int32_t* tile_start;
     int32_t* gchunk_start;
     int32_t* vstart;
+    int32_t* rstart;
     // tree and gradient scratch
     int32_t* order;
     int32_t* parent;
     int32_t* pos;
     uint64_t* ek;
     float* gedge;
+    appd::BatchBlk blk;
+    uint64_t* lists;
+    int32_t* tstats;
     size_t table_bytes;  // bytes of the region uploaded by prepare
     size_t total_bytes;
 };
@@ -59,6 +63,7 @@ Tables carve(void* ws, int G, int64_t total_n) {
     t.tile_start = (int32_t*)take(4 * (size_t)G);
     t.gchunk_start = (int32_t*)take(4 * (size_t)G);
     t.vstart = (int32_t*)take(4 * (size_t)G);
+    t.rstart = (int32_t*)take(4 * (size_t)G);
     t.table_bytes = off;
     t.xoff = (int64_t*)take(8 * (size_t)G);
     t.order = (int32_t*)take(4 * (size_t)total_n);
@@ -66,6 +71,14 @@ Tables carve(void* ws, int G, int64_t total_n) {
     t.pos = (int32_t*)take(4 * (size_t)total_n);
     t.ek = (uint64_t*)take(8 * (size_t)total_n);
     t.gedge = (float*)take(4 * (size_t)total_n);
+    t.blk.sp = (uint16_t*)take(2 * (size_t)total_n);
+    t.blk.slot = (uint16_t*)take(2 * (size_t)total_n);
+    t.blk.code = (uint32_t*)take(4 * (size_t)total_n);
+    t.blk.dM = (float*)take(4 * (size_t)total_n);
+    t.blk.dI = (int32_t*)take(4 * (size_t)total_n);
+    t.blk.sorted = (uint64_t*)take(8 * (size_t)total_n);
+    t.lists = (uint64_t*)take(8 * 16 * (size_t)total_n);
+    t.tstats = (int32_t*)take(4 * (size_t)G);
     t.total_bytes = off;
     return t;
 }
@@ -90,12 +103,17 @@ appd::BatchPlan device_plan(const appd_batch_plan* p, const Tables& t) {
     bp.perm = t.perm;
     bp.noff = t.noff;
     bp.chunk_start = t.chunk_start;
+    bp.rstart = t.rstart;
+    bp.lists = t.lists;
+    bp.tstats = t.tstats;
     for (int c = 0; c < appd::kBatchClasses; ++c) {
         bp.class_first[c] = p->class_first[c];
         bp.class_count[c] = p->class_count[c];
         bp.class_chunks[c] = p->class_chunks[c];
         bp.class_rows[c] = p->class_rows[c];
         bp.class_threads[c] = p->class_threads[c];
+        bp.class_tree[c] = p->class_tree[c];
+        bp.class_vertices[c] = p->class_vertices[c];
     }
     bp.streams = p->streams;
     bp.split_count = p->split_count;
@@ -122,6 +140,7 @@ uint64_t tables_key_of(const appd_batch_plan* p) {
         mix(p->class_count[c]);
         mix(p->class_rows[c]);
         mix(p->class_chunks[c]);
+        mix(p->class_vertices[c]);
     }
     mix(p->split_count);
     mix(p->split_chunks);
@@ -143,6 +162,8 @@ bool schedule_ok(const appd_batch_plan* p) {
         if (!p->class_count[c]) continue;
         if (p->class_rows[c] < 1 || p->class_rows[c] > APPD_BATCH_MAX_N) return false;
         if (!appd::batch_threads_ok(c, p->class_threads[c])) return false;
+        if (p->class_tree[c] != APPD_BATCH_TREE_PRIM && p->class_tree[c] != APPD_BATCH_TREE_BORUVKA)
+            return false;
     }
     return true;
 }
@@ -187,13 +208,15 @@ void build_chunks(const int32_t* ns_host, const std::vector<int32_t>& perm, appd
     p->tables_key = tables_key_of(p);
 }
 
-// Default schedule: Prim workgroups of 64 threads up to n = 256, 256 threads
-// above; 16 rows per fill item; classes in order on the caller's stream.
+// Default schedule: Boruvka trees for every class (Prim workgroups, when a
+// schedule picks Prim, of 64 threads up to n = 256 and 256 above); 16 rows per
+// fill item; classes in order on the caller's stream.
 void default_schedule(appd_batch_plan* p) {
     static const int threads[appd::kBatchClasses] = {64, 64, 64, 256, 256, 256};
     for (int c = 0; c < appd::kBatchClasses; ++c) {
         p->class_threads[c] = threads[c];
         p->class_rows[c] = 16;
+        p->class_tree[c] = APPD_BATCH_TREE_BORUVKA;
     }
     p->streams = 1;
 }
@@ -233,7 +256,7 @@ int appd_batch_prepare(const int32_t* ns_host, int num_graphs, void* ws, size_t 
     std::stable_sort(perm.begin(), perm.end(),
                      [&](int a, int b) { return ns_host[a] > ns_host[b]; });
     std::vector<int64_t> offsets(G), noff(G);
-    std::vector<int32_t> chunk_start(G), tile_start(G), gchunk_start(G), vstart(G);
+    std::vector<int32_t> chunk_start(G), tile_start(G), gchunk_start(G), vstart(G), rstart(G);
     int64_t o = 0, no = 0;
     int64_t tiles = 0, gch = 0, vb = 0;
     const int tile = appd::pairwise_tile();
@@ -259,11 +282,16 @@ int appd_batch_prepare(const int32_t* ns_host, int num_graphs, void* ws, size_t 
     p.chain_blocks = (int)vb;
     // classes are contiguous in perm (n descending, class ascending in n)
     for (int c = 0; c < appd::kBatchClasses; ++c) p.class_first[c] = -1;
+    int64_t rs = 0;
     for (int i = 0; i < G; ++i) {
         const int c = appd::batch_class_of(ns_host[perm[i]]);
         if (p.class_first[c] < 0) p.class_first[c] = i;
         p.class_count[c]++;
+        p.class_vertices[c] += ns_host[perm[i]];
+        rstart[i] = (int32_t)rs;
+        rs += ns_host[perm[i]];
     }
+    if (rs > INT32_MAX) return fail(APPD_EINVAL);
     for (int c = 0; c < appd::kBatchClasses; ++c)
         if (p.class_first[c] < 0) p.class_first[c] = 0;
     default_schedule(&p);
@@ -280,6 +308,7 @@ int appd_batch_prepare(const int32_t* ns_host, int num_graphs, void* ws, size_t 
     std::memcpy(h.tile_start, tile_start.data(), 4 * (size_t)G);
     std::memcpy(h.gchunk_start, gchunk_start.data(), 4 * (size_t)G);
     std::memcpy(h.vstart, vstart.data(), 4 * (size_t)G);
+    std::memcpy(h.rstart, rstart.data(), 4 * (size_t)G);
     hipStream_t s = (hipStream_t)stream;
     if (hipMemcpyAsync(ws, img.data(), lay.table_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
@@ -343,8 +372,8 @@ int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan*
                 float tt = 0.f;
                 for (int rep = 0; rep < 3; ++rep) {  // one warm-up, two timed
                     if (rep == 1 && (e = hipEventRecord(e0, s)) != hipSuccess) return hip_fail(e);
-                    if ((e = appd::run_batched(W, t.offsets, t.ns, bp, tree, APPD_MINIMAX, M, idx,
-                                               s)) != hipSuccess)
+                    if ((e = appd::run_batched(W, t.offsets, t.ns, bp, tree, t.blk, APPD_MINIMAX, M,
+                                               idx, s)) != hipSuccess)
                         return hip_fail(e);
                 }
                 if ((e = hipEventRecord(e1, s)) != hipSuccess ||
@@ -397,6 +426,17 @@ int appd_batch_set_schedule(appd_batch_plan* plan, void* ws, void* stream) {
     return ok();
 }
 
+int appd_batch_tree_stats(const appd_batch_plan* plan, const void* ws, int32_t* stats,
+                          void* stream) {
+    if (!stats || !plan_ok(plan, const_cast<void*>(ws))) return fail(APPD_EINVAL);
+    Tables t = carve(const_cast<void*>(ws), plan->num_graphs, plan->total_n);
+    hipStream_t s = (hipStream_t)stream;
+    if (hipStreamSynchronize(s) != hipSuccess ||
+        hipMemcpy(stats, t.tstats, 4 * (size_t)plan->num_graphs, hipMemcpyDeviceToHost) != hipSuccess)
+        return hip_status(hipErrorUnknown);
+    return ok();
+}
+
 int appd_forward_batched(const float* W, int mode, float* M, int32_t* idx, int32_t* parent,
                          const appd_batch_plan* plan, void* ws, void* stream) {
     if (!W || !M || !idx || !plan_ok(plan, ws) || !schedule_ok(plan) ||
@@ -405,7 +445,7 @@ int appd_forward_batched(const float* W, int mode, float* M, int32_t* idx, int32
     Tables t = carve(ws, plan->num_graphs, plan->total_n);
     appd::BatchTree tree{t.order, t.ek, t.pos, parent ? parent : t.parent};
     appd::BatchPlan bp = device_plan(plan, t);
-    return hip_status(appd::run_batched(W, t.offsets, t.ns, bp, tree, mode, M, idx,
+    return hip_status(appd::run_batched(W, t.offsets, t.ns, bp, tree, t.blk, mode, M, idx,
                                         (hipStream_t)stream));
 }
 

@@ -21,6 +21,7 @@
 // gap[k] = ek[k], slot_of_col = pos) and no prep kernel is needed.
 #include <mutex>
 
+#include "appd.h"
 #include "appd_fill.h"
 #include "appd_internal.h"
 #include "appd_prim.h"
@@ -35,10 +36,12 @@ __global__ __launch_bounds__(NT) void prim_batched_kernel(const float* __restric
                                                           const int32_t* __restrict__ ns,
                                                           const int32_t* __restrict__ perm,
                                                           const int64_t* __restrict__ noff,
-                                                          int first, BatchTree tree) {
+                                                          int first, BatchTree tree,
+                                                          int32_t* __restrict__ tstats) {
     __shared__ uint64_t red_key[2 * (NT / kWave)];
     __shared__ int32_t red_v[2 * (NT / kWave)];
     const int g = perm[first + blockIdx.x];
+    if (threadIdx.x == 0) tstats[g] = -1;  // Prim's algorithm
     const int n = ns[g];
     const int64_t o = noff[g];
     PrimOut out{tree.order + o, tree.ek + o, tree.pos + o, tree.parent + o};
@@ -90,6 +93,91 @@ __global__ __launch_bounds__(kBatchFillThreads) void fill_batched_kernel(
                                        idx + offsets[g], NWV);
 }
 
+// Classes of graphs with n > 256 are filled on 32-bit slot codes like the
+// single-graph path: one prep workgroup per (graph, column block of 1024)
+// builds the block's tables (fill_prep_block), then the coded fill writes the
+// rows.  Its per-row work does not grow with the 64-bit keys, and rows whose M
+// and idx starts are misaligned alike are written four columns per 16-byte
+// store.  Smaller graphs keep the 64-bit fill above (a 1024-column block would
+// be mostly padding for them).
+constexpr int kCodedCB = 1024;
+constexpr int kCodedMinClass = 3;  // n in (256, 512] and above
+constexpr int kCodedBits = (2048 + 31) / 32;
+
+template <bool WIDEST>
+__global__ __launch_bounds__(kCodedCB) void fill_prep_batched_kernel(
+    const int32_t* __restrict__ ns, const int32_t* __restrict__ perm,
+    const int64_t* __restrict__ noff, int first, int bpg, BatchTree tree, BatchBlk blk) {
+    __shared__ uint32_t keys[kCodedCB];
+    __shared__ uint32_t bits[kCodedBits];
+    __shared__ int32_t wpre[kCodedBits];
+    __shared__ uint64_t gap[kCodedCB];
+    __shared__ uint64_t srt[kCodedCB];
+    const int gi = first + (int)blockIdx.x / bpg, b = (int)blockIdx.x % bpg;
+    const int g = perm[gi];
+    const int n = ns[g];
+    if (b * kCodedCB >= n) return;  // whole workgroup: no barrier is skipped by part of it
+    const int64_t o = noff[g];
+    fill_prep_block<kCodedCB, WIDEST>(tree.pos + o, tree.ek + o, n, b, blk.sp + o, blk.slot + o,
+                                      blk.code + o, blk.dM + o, blk.dI + o, blk.sorted + o, keys,
+                                      bits, wpre, gap, srt);
+}
+
+template <bool WIDEST>
+__global__ __launch_bounds__(kBatchFillThreads) void fill_coded_batched_kernel(
+    const int64_t* __restrict__ offsets, const int32_t* __restrict__ ns,
+    const int32_t* __restrict__ perm, const int64_t* __restrict__ noff,
+    const int32_t* __restrict__ chunk_start, int first, int count, int chunk_base, int rows,
+    BatchTree tree, BatchBlk blk, float* __restrict__ M, int32_t* __restrict__ idx) {
+    constexpr int CB = kCodedCB;
+    constexpr int NWV = kBatchFillThreads / kWave;
+    __shared__ uint16_t s_sp[CB];
+    __shared__ __align__(16) uint16_t s_slot[CB];
+    __shared__ uint64_t s_sorted[CB];
+    __shared__ float s_dM[CB + 2 * NWV];
+    __shared__ int32_t s_dI[CB + 2 * NWV];
+    __shared__ uint32_t s_R[NWV][CB];
+    // graph and row chunk as in fill_batched_kernel; blockIdx.y = column block
+    const int b = chunk_base + (int)blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (chunk_start[first + mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const int gi = first + lo;
+    const int g = perm[gi];
+    const int n = ns[g];
+    const int chunk = b - chunk_start[gi];
+    const int j0 = (int)blockIdx.y * CB;
+    if (chunk < 0 || (int64_t)chunk * rows >= n || j0 >= n) return;
+    const int cnt = min(CB, n - j0);
+    const int64_t o = noff[g];
+    for (int k = threadIdx.x; k < CB; k += kBatchFillThreads) {
+        const bool in = k < cnt;
+        s_sp[k] = in ? blk.sp[o + j0 + k] : (uint16_t)0xffff;
+        s_slot[k] = in ? blk.slot[o + j0 + k] : (uint16_t)0;
+        s_sorted[k] = in ? blk.sorted[o + j0 + k] : ~0ull;
+        s_dM[k] = in ? blk.dM[o + j0 + k] : 0.0f;
+        s_dI[k] = in ? blk.dI[o + j0 + k] : -1;
+    }
+    __syncthreads();
+    const int r0 = chunk * rows;
+    const int r1 = min(n, r0 + rows);
+    float* Mg = M + offsets[g];
+    int32_t* Ig = idx + offsets[g];
+    const bool vec = (n % 4 == 0) && ((((uintptr_t)Mg) | ((uintptr_t)Ig)) & 15u) == 0;
+    uint32_t* row_buf = s_R[threadIdx.x / kWave];
+    if (vec)
+        fill_rows_block_coded<CB, WIDEST, true, true>(tree.pos + o, tree.ek + o, n, j0, cnt, r0, r1, s_sp,
+                                                s_slot, blk.code + o + j0, s_sorted, s_dM, s_dI,
+                                                row_buf, Mg, Ig, NWV);
+    else
+        fill_rows_block_coded<CB, WIDEST, false, true>(tree.pos + o, tree.ek + o, n, j0, cnt, r0, r1,
+                                                 s_sp, s_slot, blk.code + o + j0, s_sorted, s_dM,
+                                                 s_dI, row_buf, Mg, Ig, NWV);
+}
+
 int batch_class_of(int n) {
     for (int c = 0; c < kBatchClasses; ++c)
         if (n <= kClassMaxN[c]) return c;
@@ -116,7 +204,8 @@ static hipError_t launch_prim_class(int c, int threads, int first, int count, co
     if (threads == NT && ch == CH) {                                             \
         APPD_LAUNCH("prim_batched_kernel", s,                                    \
                     prim_batched_kernel<NT, CH, WIDEST><<<count, NT, 0, s>>>(    \
-                        W, offsets, ns, plan.perm, plan.noff, first, tree));     \
+                        W, offsets, ns, plan.perm, plan.noff, first, tree,       \
+                        plan.tstats));                                           \
         return hipGetLastError();                                                \
     }
     APPD_PRIM_B(64, 1)
@@ -144,8 +233,21 @@ template <bool WIDEST>
 static hipError_t launch_fill_class(int c, int first, int count, int chunk_base, int chunks,
                                     int rows,
                                     const int64_t* offsets, const int32_t* ns,
-                                    const BatchPlan& plan, const BatchTree& tree, float* M,
-                                    int32_t* idx, hipStream_t s) {
+                                    const BatchPlan& plan, const BatchTree& tree,
+                                    const BatchBlk& blk, float* M, int32_t* idx, hipStream_t s) {
+    if (c >= kCodedMinClass) {
+        const int bpg = (kClassMaxN[c] + kCodedCB - 1) / kCodedCB;
+        APPD_LAUNCH("fill_prep_batched_kernel", s,
+                    fill_prep_batched_kernel<WIDEST><<<count * bpg, kCodedCB, 0, s>>>(
+                        ns, plan.perm, plan.noff, first, bpg, tree, blk));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        APPD_LAUNCH("fill_coded_batched_kernel", s,
+                    fill_coded_batched_kernel<WIDEST><<<dim3(chunks, bpg), kBatchFillThreads, 0, s>>>(
+                        offsets, ns, plan.perm, plan.noff, plan.chunk_start, first, count,
+                        chunk_base, rows, tree, blk, M, idx));
+        return hipGetLastError();
+    }
 #define APPD_FILL_B(CC, CB)                                                           \
     if (c == CC) {                                                                    \
         APPD_LAUNCH("fill_batched_kernel", s,                                         \
@@ -204,8 +306,8 @@ hipError_t side_streams(SideStreams** out) {
 
 template <bool WIDEST>
 static hipError_t run_batched_t(const float* W, const int64_t* offsets, const int32_t* ns,
-                                const BatchPlan& plan, const BatchTree& tree, float* M,
-                                int32_t* idx, hipStream_t s) {
+                                const BatchPlan& plan, const BatchTree& tree,
+                                const BatchBlk& blk, float* M, int32_t* idx, hipStream_t s) {
     // classes in launch order: largest first
     int cls[kBatchClasses], nc = 0;
     for (int c = kBatchClasses - 1; c >= 0; --c)
@@ -236,29 +338,35 @@ static hipError_t run_batched_t(const float* W, const int64_t* offsets, const in
         const int c = cls[j];
         const int first = plan.class_first[c], count = plan.class_count[c];
         const int rows = plan.class_rows[c], chunks = plan.class_chunks[c];
+        // trees of graphs first .. first + cnt - 1 of class c (for the pass grid
+        // of Boruvka, rows_bound >= their total n; surplus waves exit)
+        auto trees = [&](int f0, int cnt, int rows_bound, hipStream_t cs) -> hipError_t {
+            return plan.class_tree[c] == APPD_BATCH_TREE_BORUVKA
+                       ? launch_btree(c, f0, cnt, rows_bound, WIDEST ? 1 : 0, W, offsets, ns, plan,
+                                      tree, plan.lists, cs)
+                       : launch_prim_class<WIDEST>(c, plan.class_threads[c], f0, cnt, W, offsets,
+                                                   ns, plan, tree, cs);
+        };
         if (j == 0 && split) {
             const int h = plan.split_count, hc = plan.split_chunks;
-            e = launch_prim_class<WIDEST>(c, plan.class_threads[c], first, h, W, offsets, ns,
-                                          plan, tree, st[0]);
+            e = trees(first, h, min(plan.class_vertices[c], h * kClassMaxN[c]), st[0]);
             if (e != hipSuccess) return e;
-            e = launch_fill_class<WIDEST>(c, first, h, 0, hc, rows, offsets, ns, plan, tree, M,
-                                          idx, st[0]);
+            e = launch_fill_class<WIDEST>(c, first, h, 0, hc, rows, offsets, ns, plan, tree, blk,
+                                          M, idx, st[0]);
             if (e != hipSuccess) return e;
-            e = launch_prim_class<WIDEST>(c, plan.class_threads[c], first + h, count - h, W,
-                                          offsets, ns, plan, tree, st[1]);
+            e = trees(first + h, count - h, plan.class_vertices[c], st[1]);
             if (e != hipSuccess) return e;
             e = launch_fill_class<WIDEST>(c, first + h, count - h, hc, chunks - hc, rows,
-                                          offsets, ns, plan, tree, M, idx, st[1]);
+                                          offsets, ns, plan, tree, blk, M, idx, st[1]);
             if (e != hipSuccess) return e;
             continue;
         }
         hipStream_t cs =
             (j == 0 || nstreams == 1) ? st[0] : st[others0 + (j - 1) % (nstreams - others0)];
-        e = launch_prim_class<WIDEST>(c, plan.class_threads[c], first, count, W, offsets, ns,
-                                      plan, tree, cs);
+        e = trees(first, count, plan.class_vertices[c], cs);
         if (e != hipSuccess) return e;
         e = launch_fill_class<WIDEST>(c, first, count, 0, chunks, rows, offsets, ns, plan, tree,
-                                      M, idx, cs);
+                                      blk, M, idx, cs);
         if (e != hipSuccess) return e;
     }
     if (nstreams > 1) {
@@ -271,10 +379,10 @@ static hipError_t run_batched_t(const float* W, const int64_t* offsets, const in
 }
 
 hipError_t run_batched(const float* W, const int64_t* offsets, const int32_t* ns,
-                       const BatchPlan& plan, const BatchTree& tree, int mode, float* M,
-                       int32_t* idx, hipStream_t s) {
-    return mode == 1 ? run_batched_t<true>(W, offsets, ns, plan, tree, M, idx, s)
-                     : run_batched_t<false>(W, offsets, ns, plan, tree, M, idx, s);
+                       const BatchPlan& plan, const BatchTree& tree, const BatchBlk& blk,
+                       int mode, float* M, int32_t* idx, hipStream_t s) {
+    return mode == 1 ? run_batched_t<true>(W, offsets, ns, plan, tree, blk, M, idx, s)
+                     : run_batched_t<false>(W, offsets, ns, plan, tree, blk, M, idx, s);
 }
 
 }  // namespace appd

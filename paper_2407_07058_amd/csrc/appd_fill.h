@@ -349,7 +349,11 @@ __device__ __forceinline__ void fill_rows_block(const int32_t* __restrict__ pos,
 // last-level cache, and lines left dirty there would be written back during
 // whatever runs next (the following pass over W).  s_R: this wave's row
 // buffer of CB codes; s_dM / s_dI: CB + 2 * nwaves entries.
-template <int CB, bool WIDEST, bool VEC>
+// EXACT (short blocks, the batched fill): the 16-byte stores cover only the
+// block's columns; otherwise every lane issues CB / 256 of them, a short block
+// repeating its last four columns, so that the count of memory operations per
+// row is fixed.
+template <int CB, bool WIDEST, bool VEC, bool EXACT = false>
 __device__ __forceinline__ void fill_rows_block_coded(
     const int32_t* __restrict__ pos, const uint64_t* __restrict__ ek, int n, int j0, int cnt,
     int r0, int r1, const uint16_t* s_sp, const uint16_t* s_slot,
@@ -524,6 +528,7 @@ __device__ __forceinline__ void fill_rows_block_coded(
             // columns (the same values to the same addresses)
 #pragma unroll
             for (int it = 0; it < CB / (4 * kWave); ++it) {
+                if (EXACT && lane * 4 + it * 4 * kWave >= cnt) break;
                 const int c = min(lane * 4 + it * 4 * kWave, cnt - 4);
                 const uint64_t sl = *(const uint64_t*)(s_slot + c);  // 4 slots
                 const uint32_t c0 = s_R[sl & 0xffff] & kCodeMask;
@@ -536,10 +541,35 @@ __device__ __forceinline__ void fill_rows_block_coded(
                 __builtin_nontemporal_store(iv, (i4v*)(irow + c));
             }
         } else {
-            for (int c = lane; c < cnt; c += kWave) {
+            auto put1 = [&](int c) {
                 const uint32_t cd = s_R[s_slot[c]] & kCodeMask;
                 __builtin_nontemporal_store(s_dM[cd], mrow + c);
                 __builtin_nontemporal_store(s_dI[cd], irow + c);
+            };
+            // A row may start at any 4-byte boundary (n % 4 != 0, or graphs
+            // packed back to back).  When the M and idx rows are misaligned
+            // alike: the columns up to the first 16-byte boundary and the last
+            // (cnt - h) % 4 one lane each, the rest four per 16-byte store.
+            const int mis = (int)(((uintptr_t)mrow >> 2) & 3u);
+            if (mis == (int)(((uintptr_t)irow >> 2) & 3u)) {
+                const int h = min(cnt, (4 - mis) & 3);
+                const int nq = (cnt - h) >> 2;
+                const int tail0 = h + 4 * nq;
+                if (lane < h) put1(lane);
+                if (lane < cnt - tail0) put1(tail0 + lane);
+                for (int m = lane; m < nq; m += kWave) {
+                    const int c = h + 4 * m;
+                    const uint32_t c0 = s_R[s_slot[c]] & kCodeMask;
+                    const uint32_t c1 = s_R[s_slot[c + 1]] & kCodeMask;
+                    const uint32_t c2 = s_R[s_slot[c + 2]] & kCodeMask;
+                    const uint32_t c3 = s_R[s_slot[c + 3]] & kCodeMask;
+                    const f4v mv = {s_dM[c0], s_dM[c1], s_dM[c2], s_dM[c3]};
+                    const i4v iv = {s_dI[c0], s_dI[c1], s_dI[c2], s_dI[c3]};
+                    __builtin_nontemporal_store(mv, (f4v*)(mrow + c));
+                    __builtin_nontemporal_store(iv, (i4v*)(irow + c));
+                }
+            } else {
+                for (int c = lane; c < cnt; c += kWave) put1(c);
             }
         }
         wave_lds_sync();

@@ -68,10 +68,27 @@ struct BatchTree {
     int32_t* parent;
 };
 
+// Per-graph column-block tables of the coded fill (graphs with n > 256): the
+// entries of graph g's block b sit at noff[g] + 1024 * b + k, k < the block's
+// column count (see fill_prep_block).
+struct BatchBlk {
+    uint16_t* sp;
+    uint16_t* slot;
+    uint32_t* code;
+    float* dM;
+    int32_t* dI;
+    uint64_t* sorted;
+};
+
 struct BatchPlan {
     const int32_t* perm;         // [G] graph ids, n descending (device)
     const int64_t* noff;         // [G] start of graph g's O(n) arrays (device, by graph id)
     const int32_t* chunk_start;  // [G] first fill item of perm[i] within its class (device)
+    const int32_t* rstart;       // [G] sum of n over perm[0 .. i) (device)
+    uint64_t* lists;             // candidate lists of the Boruvka classes, K per vertex
+    int32_t* tstats;             // [G] per graph, by graph id: how its tree was found
+    int class_tree[kBatchClasses];
+    int class_vertices[kBatchClasses];
     int class_first[kBatchClasses];
     int class_count[kBatchClasses];
     int class_chunks[kBatchClasses];
@@ -83,10 +100,13 @@ struct BatchPlan {
 };
 
 int batch_class_of(int n);
+hipError_t launch_btree(int c, int first, int count, int rows_in_class, int mode, const float* W,
+                        const int64_t* offsets, const int32_t* ns, const BatchPlan& plan,
+                        const BatchTree& tree, uint64_t* lists, hipStream_t s);
 bool batch_threads_ok(int c, int threads);
 hipError_t run_batched(const float* W, const int64_t* offsets, const int32_t* ns,
-                       const BatchPlan& plan, const BatchTree& tree, int mode, float* M,
-                       int32_t* idx, hipStream_t s);
+                       const BatchPlan& plan, const BatchTree& tree, const BatchBlk& blk,
+                       int mode, float* M, int32_t* idx, hipStream_t s);
 
 // ---- points / gradients
 hipError_t run_pairwise(const float* X, const int64_t* xoff, const int64_t* offsets,

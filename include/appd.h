@@ -231,6 +231,8 @@ typedef struct {
     int class_tree[APPD_BATCH_CLASSES];     /* how the class's trees are found:
                                                APPD_BATCH_TREE_PRIM or APPD_BATCH_TREE_BORUVKA */
     int class_vertices[APPD_BATCH_CLASSES]; /* sum of n over the class's graphs */
+    int split_vertices; /* sum of n over the graphs launched on their own (set with
+                           split_count) */
 } appd_batch_plan;
 
 /* class_tree values.  Prim: one workgroup per graph runs Prim's algorithm
@@ -256,10 +258,11 @@ int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan*
                         void* stream, float* best_ms);
 
 /* Sets a schedule by hand (for experiments and tests): the plan's
- * class_threads, class_rows and streams, and split_count (0: no cut, else the
- * number of the largest class's biggest graphs launched on their own).  The
- * device work tables are rebuilt for it and the derived fields (class_chunks,
- * split_chunks, tables_key) set.  Checks the schedule (APPD_EINVAL if it is not
+ * class_threads, class_rows, class_tree and streams, and split_count (0: no
+ * cut, -1: a cut into two parts of about equal work, else the number of the
+ * largest class's biggest graphs launched on their own).  The device work
+ * tables are rebuilt for it and the derived fields (class_chunks, split_count,
+ * split_chunks, split_vertices, tables_key) set.  Checks the schedule (APPD_EINVAL if it is not
  * one the kernels support); synchronises and is not capturable. */
 int appd_batch_set_schedule(appd_batch_plan* plan, void* ws, void* stream);
 

@@ -95,7 +95,8 @@ class BatchPlan(ctypes.Structure):
                 ("ws_bytes", ctypes.c_size_t), ("split_count", ctypes.c_int),
                 ("split_chunks", ctypes.c_int), ("tables_key", ctypes.c_uint64),
                 ("class_tree", ctypes.c_int * BATCH_CLASSES),
-                ("class_vertices", ctypes.c_int * BATCH_CLASSES)]
+                ("class_vertices", ctypes.c_int * BATCH_CLASSES),
+                ("split_vertices", ctypes.c_int)]
 
 _lib = None
 

@@ -118,6 +118,7 @@ appd::BatchPlan device_plan(const appd_batch_plan* p, const Tables& t) {
     bp.streams = p->streams;
     bp.split_count = p->split_count;
     bp.split_chunks = p->split_chunks;
+    bp.split_vertices = p->split_vertices;
     return bp;
 }
 
@@ -144,6 +145,7 @@ uint64_t tables_key_of(const appd_batch_plan* p) {
     }
     mix(p->split_count);
     mix(p->split_chunks);
+    mix(p->split_vertices);
     return h;
 }
 
@@ -154,7 +156,7 @@ bool schedule_ok(const appd_batch_plan* p) {
     int top = -1;  // the largest class present
     for (int c = 0; c < appd::kBatchClasses; ++c)
         if (p->class_count[c]) top = c;
-    if (p->split_count < 0 || p->split_chunks < 0) return false;
+    if (p->split_count < 0 || p->split_chunks < 0 || p->split_vertices < 0) return false;
     if (p->split_count && (top < 0 || p->split_count >= p->class_count[top] ||
                            p->split_chunks < 1 || p->split_chunks >= p->class_chunks[top]))
         return false;
@@ -170,11 +172,14 @@ bool schedule_ok(const appd_batch_plan* p) {
 
 // Fill work items per class for the plan's rows per item; chunk_start[i] is the
 // first item of the i-th graph (n-descending order) within its class.  split:
-// 0 no cut; -1 the largest class is cut after its graphs of n >= 0.84 n_max (a
-// Prim chain grows with n and a fill with n^2, and for sizes spread evenly on a
-// log scale over one class (n_max / 2, n_max] this cut gives the two parts
-// about the same Prim + fill time); h > 0 the cut after its first h graphs.
-// Sets class_chunks, split_count, split_chunks and the tables' stamp.
+// 0 no cut; -1 a cut of the largest class into two parts of about equal work:
+// with Boruvka trees (a pass over W and a fill, both n^2 per graph) where the
+// running sum of n^2 reaches half the class's, with Prim trees after its graphs
+// of n >= 0.84 n_max (a Prim chain grows with n and a fill with n^2, and for
+// sizes spread evenly on a log scale over one class (n_max / 2, n_max] this cut
+// gives the two parts about the same Prim + fill time); h > 0 the cut after its
+// first h graphs.  Sets class_chunks, split_count, split_chunks, split_vertices
+// and the tables' stamp.
 void build_chunks(const int32_t* ns_host, const std::vector<int32_t>& perm, appd_batch_plan* p,
                   std::vector<int32_t>& chunk_start, int split) {
     const int G = p->num_graphs;
@@ -187,7 +192,7 @@ void build_chunks(const int32_t* ns_host, const std::vector<int32_t>& perm, appd
         chunk_start[i] = p->class_chunks[c];
         p->class_chunks[c] += (n + rows - 1) / rows;
     }
-    p->split_count = p->split_chunks = 0;
+    p->split_count = p->split_chunks = p->split_vertices = 0;
     int top = -1;
     for (int c = 0; c < appd::kBatchClasses; ++c)
         if (p->class_count[c]) top = c;
@@ -195,7 +200,15 @@ void build_chunks(const int32_t* ns_host, const std::vector<int32_t>& perm, appd
         const int first = p->class_first[top], count = p->class_count[top];
         const int nmax = ns_host[perm[first]];
         int h = split;
-        if (split < 0) {
+        if (split < 0 && p->class_tree[top] == APPD_BATCH_TREE_BORUVKA) {
+            int64_t all = 0, run = 0;
+            for (int i = 0; i < count; ++i) all += (int64_t)ns_host[perm[first + i]] * ns_host[perm[first + i]];
+            h = 0;
+            while (h < count && 2 * run < all) {
+                run += (int64_t)ns_host[perm[first + h]] * ns_host[perm[first + h]];
+                ++h;
+            }
+        } else if (split < 0) {
             h = 0;
             while (h < count && 100 * (int64_t)ns_host[perm[first + h]] >= 84 * (int64_t)nmax) ++h;
         }
@@ -203,6 +216,7 @@ void build_chunks(const int32_t* ns_host, const std::vector<int32_t>& perm, appd
             chunk_start[first + h] < p->class_chunks[top]) {
             p->split_count = h;
             p->split_chunks = chunk_start[first + h];
+            for (int i = 0; i < h; ++i) p->split_vertices += ns_host[perm[first + i]];
         }
     }
     p->tables_key = tables_key_of(p);
@@ -399,7 +413,7 @@ int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan*
 
 int appd_batch_set_schedule(appd_batch_plan* plan, void* ws, void* stream) {
     if (!plan_ok(plan, ws) || plan->streams < 1 || plan->streams > appd::kBatchClasses ||
-        plan->split_count < 0)
+        plan->split_count < -1)
         return fail(APPD_EINVAL);
     for (int c = 0; c < appd::kBatchClasses; ++c) {
         if (!plan->class_count[c]) continue;

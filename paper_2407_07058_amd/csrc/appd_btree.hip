@@ -63,6 +63,7 @@ __global__ __launch_bounds__(kBtPassThreads) void btree_pass_kernel(
     const int32_t* __restrict__ ns, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ noff, const int32_t* __restrict__ rstart, int first, int count,
     uint64_t* __restrict__ lists) {
+    __shared__ uint64_t s_buf[kBtPassThreads / kWave][kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int r = __builtin_amdgcn_readfirstlane(
         rstart[first] + (int)blockIdx.x * (kBtPassThreads / kWave) + (int)threadIdx.x / kWave);
@@ -73,8 +74,10 @@ __global__ __launch_bounds__(kBtPassThreads) void btree_pass_kernel(
     const int n = ns[g];
     const int u = r - rstart[i];
     const float* row = W + offsets[g] + (size_t)u * n;
-    const uint64_t mine = row_topk<WIDEST, false, false, E, kBtK>(
-        row, n, u, [](int) { return 0; }, [](int) { return make_int4(0, 0, 0, 0); });
+    uint64_t mine;
+    if (!row_topk_compact<WIDEST, E, kBtK>(row, n, u, s_buf[threadIdx.x / kWave], &mine))
+        mine = row_topk<WIDEST, false, false, E, kBtK>(
+            row, n, u, [](int) { return 0; }, [](int) { return make_int4(0, 0, 0, 0); });
     if (lane < kBtK) lists[(size_t)(noff[g] + u) * kBtK + lane] = mine;
 }
 
@@ -176,7 +179,7 @@ __global__ __launch_bounds__(NT) void btree_finish_kernel(
     const float* __restrict__ Wall, const int64_t* __restrict__ offsets,
     const int32_t* __restrict__ ns, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ noff, int first, int nmax, uint64_t* __restrict__ lists_all,
-    BatchTree tree, int32_t* __restrict__ tstats) {
+    BatchTree tree, int32_t* __restrict__ tstats, BatchBlk blk) {
     constexpr int NW = NT / kWave;
     extern __shared__ uint64_t s_dyn[];
     __shared__ int s_segv[NT], s_segh[NT];
@@ -194,6 +197,9 @@ __global__ __launch_bounds__(NT) void btree_finish_kernel(
     if (n == 1) {
         if (t == 0) {
             tstats[g] = 1 << 8;
+            blk.slot[o] = 0;
+            blk.dM[o] = 0.0f;
+            blk.dI[o] = -1;
             out.order[0] = 0;
             out.ek[0] = 0;
             out.pos[0] = 0;
@@ -371,6 +377,27 @@ __global__ __launch_bounds__(NT) void btree_finish_kernel(
         // the lists could not finish the tree: Prim's algorithm (same outputs)
         __syncthreads();
         prim_run<NT, CH, WIDEST>(W, n, out, red_key, red_v);
+        __syncthreads();
+        // the fill's rank tables from Prim's attachment keys
+        uint64_t* skey = (uint64_t*)L.d4;
+        for (int i = t; i < nmax; i += NT) {
+            skey[i] = (i >= 1 && i < n) ? out.ek[i] : ~0ull;  // position i's key
+            L.comp[i] = (uint16_t)i;
+        }
+        bt_bitonic<NT>(skey, L.comp, nmax);
+        for (int r = t; r < n; r += NT) {
+            if (r == 0) {
+                blk.slot[o] = 0;
+                blk.dM[o] = 0.0f;
+                blk.dI[o] = -1;
+                continue;
+            }
+            const int k = L.comp[r - 1];  // position of the key of rank r - 1
+            const uint64_t key = skey[r - 1];
+            blk.slot[o + k] = (uint16_t)r;
+            blk.dM[o + r] = key_weight<WIDEST>(key);
+            blk.dI[o + r] = (int32_t)(uint32_t)key;
+        }
         return;
     }
     // re-root the tree at vertex 0
@@ -504,13 +531,21 @@ __global__ __launch_bounds__(NT) void btree_finish_kernel(
         out.order[p] = v;
         out.ek[p] = keyup[v];
         out.parent[v] = v ? (int)L.par[v] : -1;
+        // the fill's tables: rank code of each position (1 + the rank of its
+        // key among the n - 1 keys; 0 at position 0), and each code's weight
+        // and flat index (code 0: the diagonal)
+        const int r = v ? rankv[v] + 1 : 0;
+        blk.slot[o + p] = (uint16_t)r;
+        blk.dM[o + r] = v ? key_weight<WIDEST>(keyup[v]) : 0.0f;
+        blk.dI[o + r] = v ? (int32_t)(uint32_t)keyup[v] : -1;
     }
 }
 
 template <bool WIDEST>
 hipError_t launch_btree_t(int c, int first, int count, int rows_in_class, const float* W,
                           const int64_t* offsets, const int32_t* ns, const BatchPlan& plan,
-                          const BatchTree& tree, uint64_t* lists, hipStream_t s) {
+                          const BatchTree& tree, const BatchBlk& blk, uint64_t* lists,
+                          hipStream_t s) {
     if (count <= 0) return hipSuccess;
     const int nmax = kClassMaxN[c];
     const int blocks = (rows_in_class + kBtPassThreads / kWave - 1) / (kBtPassThreads / kWave);
@@ -542,7 +577,7 @@ hipError_t launch_btree_t(int c, int first, int count, int rows_in_class, const 
         APPD_LAUNCH("btree_finish_kernel", s,                                                  \
                     btree_finish_kernel<NTT, CC, WIDEST><<<count, NTT, lds, s>>>(              \
                         W, offsets, ns, plan.perm, plan.noff, first, nmax, lists, tree,        \
-                        plan.tstats));                                                         \
+                        plan.tstats, blk));                                                    \
         return hipGetLastError();                                                              \
     }
     APPD_BT_FIN(256, 64)
@@ -557,11 +592,12 @@ hipError_t launch_btree_t(int c, int first, int count, int rows_in_class, const 
 
 hipError_t launch_btree(int c, int first, int count, int rows_in_class, int mode, const float* W,
                         const int64_t* offsets, const int32_t* ns, const BatchPlan& plan,
-                        const BatchTree& tree, uint64_t* lists, hipStream_t s) {
+                        const BatchTree& tree, const BatchBlk& blk, uint64_t* lists,
+                        hipStream_t s) {
     return mode == 1 ? launch_btree_t<true>(c, first, count, rows_in_class, W, offsets, ns, plan,
-                                            tree, lists, s)
+                                            tree, blk, lists, s)
                      : launch_btree_t<false>(c, first, count, rows_in_class, W, offsets, ns, plan,
-                                             tree, lists, s);
+                                             tree, blk, lists, s);
 }
 
 }  // namespace appd

@@ -89,6 +89,7 @@ struct BatchPlan {
     int32_t* tstats;             // [G] per graph, by graph id: how its tree was found
     int class_tree[kBatchClasses];
     int class_vertices[kBatchClasses];
+    int split_vertices;
     int class_first[kBatchClasses];
     int class_count[kBatchClasses];
     int class_chunks[kBatchClasses];
@@ -102,7 +103,8 @@ struct BatchPlan {
 int batch_class_of(int n);
 hipError_t launch_btree(int c, int first, int count, int rows_in_class, int mode, const float* W,
                         const int64_t* offsets, const int32_t* ns, const BatchPlan& plan,
-                        const BatchTree& tree, uint64_t* lists, hipStream_t s);
+                        const BatchTree& tree, const BatchBlk& blk, uint64_t* lists,
+                        hipStream_t s);
 bool batch_threads_ok(int c, int threads);
 hipError_t run_batched(const float* W, const int64_t* offsets, const int32_t* ns,
                        const BatchPlan& plan, const BatchTree& tree, const BatchBlk& blk,

@@ -131,4 +131,97 @@ __device__ __forceinline__ uint64_t row_topk(const float* __restrict__ row, int 
 }
 
 
+// The same KK smallest entries for a short row (n <= 64 * E, no column
+// filter) without inserting entries one at a time.  The threshold is taken as
+// above (at least KK lane minima, hence at least KK entries, lie at or below
+// it, so the KK smallest entries all do); every entry at or below it is
+// written to the wave's LDS buffer (a prefix sum over the lanes gives each
+// lane its place), one per lane is read back, and a bitonic sort across the
+// lanes orders them.  Returns false, leaving *out alone, when more than 64
+// entries lie at or below the threshold (then row_topk does the work).
+// wbuf: 64 entries of LDS owned by the calling wave.
+// The loads of a short row: column e * 64 + lane into x[e] (0 past the row).
+template <int E>
+__device__ __forceinline__ void short_row_load(const float* __restrict__ row, int n, float (&x)[E]) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int c = e * kWave + lane;
+        x[e] = c < n ? row[c] : 0.0f;
+    }
+}
+
+// row_topk_compact on values already loaded by short_row_load.
+template <bool WIDEST, int E, int KK>
+__device__ __forceinline__ bool topk_compact_vals(const float (&xr)[E], int n, int u,
+                                                  uint64_t* wbuf, uint64_t* out) {
+    static_assert(KK >= 1 && KK <= 16, "the list lives in lanes 0..15");
+    constexpr uint64_t kNone = kTopkNone;
+    const int lane = threadIdx.x & (kWave - 1);
+    float sv[E];
+    bool skip[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int c = e * kWave + lane;
+        sv[e] = WIDEST ? -xr[e] : xr[e];
+        skip[e] = c >= n || c == u;
+    }
+    float lm = INFINITY;
+#pragma unroll
+    for (int e = 0; e < E; ++e) lm = fminf(lm, skip[e] ? INFINITY : sv[e]);
+    float thr = INFINITY;
+    if (__popcll(__ballot(lm < INFINITY)) >= KK) {
+        const uint32_t km = ord32(lm) >> 16;
+        uint32_t res = 0;
+        for (int b = 15; b >= 0; --b) {
+            const uint32_t c = res | (1u << b);
+            if (__popcll(__ballot(km < c)) < KK) res = c;
+        }
+        thr = res == 0xffffu ? INFINITY : ord32_inv((res << 16) | 0xffffu);
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) cnt += (!skip[e] && sv[e] <= thr) ? 1 : 0;
+    int incl = cnt;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int y = __shfl_up(incl, d);
+        if (lane >= d) incl += y;
+    }
+    const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
+    if (total > kWave) return false;
+    int off = incl - cnt;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if (!skip[e] && sv[e] <= thr) {
+            wbuf[off] = ((uint64_t)ord32(sv[e]) << 32) | (uint32_t)(e * kWave + lane);
+            ++off;
+        }
+    }
+    wave_lds_sync();
+    uint64_t x = lane < total ? wbuf[lane] : kNone;
+    wave_lds_sync();  // the buffer may be written again for the next row
+    // ascending bitonic sort of lanes 0 .. P-1 (P: a power of two >= total, >= 16)
+    int P = 16;
+    while (P < total) P <<= 1;
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint64_t y = shfl_xor_u64(x, stride);
+            const bool up = (lane & size) == 0;
+            const bool lower = (lane & stride) == 0;
+            x = (lower == up) ? umin64(x, y) : umax64(x, y);
+        }
+    }
+    *out = lane < KK ? x : kNone;
+    return true;
+}
+
+template <bool WIDEST, int E, int KK>
+__device__ __forceinline__ bool row_topk_compact(const float* __restrict__ row, int n, int u,
+                                                 uint64_t* wbuf, uint64_t* out) {
+    float x[E];
+    short_row_load<E>(row, n, x);
+    return topk_compact_vals<WIDEST, E, KK>(x, n, u, wbuf, out);
+}
+
 }  // namespace appd

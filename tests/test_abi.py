@@ -86,17 +86,19 @@ def test_batch_plan_struct_layout_matches_header(tmp_path):
     import subprocess
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "appd.h"\n'
-                   'int main(){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(appd_batch_plan),'
+                   'int main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(appd_batch_plan),'
                    'offsetof(appd_batch_plan, class_first), offsetof(appd_batch_plan, class_threads),'
                    'offsetof(appd_batch_plan, streams), offsetof(appd_batch_plan, pair_tiles),'
-                   'offsetof(appd_batch_plan, ws_bytes), offsetof(appd_batch_plan, tables_key));'
+                   'offsetof(appd_batch_plan, ws_bytes), offsetof(appd_batch_plan, tables_key),'
+                   'offsetof(appd_batch_plan, split_vertices));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     P = appd.BatchPlan
     assert got == [ctypes.sizeof(P), P.class_first.offset, P.class_threads.offset,
-                   P.streams.offset, P.pair_tiles.offset, P.ws_bytes.offset, P.tables_key.offset]
+                   P.streams.offset, P.pair_tiles.offset, P.ws_bytes.offset, P.tables_key.offset,
+                   P.split_vertices.offset]
 
 
 def test_batch_workspace_and_bad_sizes():

@@ -32,6 +32,7 @@ struct Tables {
     int32_t* gchunk_start;
     int32_t* vstart;
     int32_t* rstart;
+    int32_t* rgraph;
     // tree and gradient scratch
     int32_t* order;
     int32_t* parent;
@@ -64,6 +65,7 @@ Tables carve(void* ws, int G, int64_t total_n) {
     t.gchunk_start = (int32_t*)take(4 * (size_t)G);
     t.vstart = (int32_t*)take(4 * (size_t)G);
     t.rstart = (int32_t*)take(4 * (size_t)G);
+    t.rgraph = (int32_t*)take(4 * (size_t)total_n);
     t.table_bytes = off;
     t.xoff = (int64_t*)take(8 * (size_t)G);
     t.order = (int32_t*)take(4 * (size_t)total_n);
@@ -104,6 +106,7 @@ appd::BatchPlan device_plan(const appd_batch_plan* p, const Tables& t) {
     bp.noff = t.noff;
     bp.chunk_start = t.chunk_start;
     bp.rstart = t.rstart;
+    bp.rgraph = t.rgraph;
     bp.lists = t.lists;
     bp.tstats = t.tstats;
     for (int c = 0; c < appd::kBatchClasses; ++c) {
@@ -323,6 +326,8 @@ int appd_batch_prepare(const int32_t* ns_host, int num_graphs, void* ws, size_t 
     std::memcpy(h.gchunk_start, gchunk_start.data(), 4 * (size_t)G);
     std::memcpy(h.vstart, vstart.data(), 4 * (size_t)G);
     std::memcpy(h.rstart, rstart.data(), 4 * (size_t)G);
+    for (int i = 0; i < G; ++i)
+        std::fill(h.rgraph + rstart[i], h.rgraph + rstart[i] + ns_host[perm[i]], (int32_t)i);
     hipStream_t s = (hipStream_t)stream;
     if (hipMemcpyAsync(ws, img.data(), lay.table_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {

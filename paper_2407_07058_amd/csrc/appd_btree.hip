@@ -9,8 +9,8 @@
 // here, per size class:
 //
 //  1. btree_pass_kernel: one wave per row of every graph of the class keeps
-//     the row's K smallest entries (row_topk, appd_topk.h) as that vertex's
-//     candidate list: a bandwidth-bound pass over the class's W.
+//     the row's K smallest entries (row_topk_rank_vals, appd_topk.h) as that
+//     vertex's candidate list: one pass over the class's W.
 //  2. btree_finish_kernel: one workgroup per graph.  Boruvka rounds on the
 //     lists, all state in LDS: a vertex's first list entry outside its
 //     component is its exact cheapest outgoing edge; a vertex whose list is
@@ -44,38 +44,30 @@ constexpr int kBtRefreshes = 8;      // refreshes of a stuck graph's lists befor
 constexpr int kBtK = 16;             // candidate list length
 constexpr uint16_t kNil16 = 0xffff;
 
-// Row r of the class (rows of its graphs in LPT order, rstart = prefix of n in
-// that order) -> graph position i (first <= i < first + count), row u.
-__device__ __forceinline__ int bt_find_graph(const int32_t* __restrict__ rstart, int first,
-                                             int count, int r) {
-    int lo = first, hi = first + count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (rstart[mid] <= r) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
+// One wave per row of the class (rows of its graphs in perm order; rgraph
+// gives each row's graph position).  The row's candidate list comes from
+// row_topk_rank_vals, or from row_topk where its candidates overflow.
 template <bool WIDEST, int E>
 __global__ __launch_bounds__(kBtPassThreads) void btree_pass_kernel(
     const float* __restrict__ W, const int64_t* __restrict__ offsets,
     const int32_t* __restrict__ ns, const int32_t* __restrict__ perm,
-    const int64_t* __restrict__ noff, const int32_t* __restrict__ rstart, int first, int count,
-    uint64_t* __restrict__ lists) {
-    __shared__ uint64_t s_buf[kBtPassThreads / kWave][kWave];
+    const int64_t* __restrict__ noff, const int32_t* __restrict__ rstart,
+    const int32_t* __restrict__ rgraph, int first, int count, uint64_t* __restrict__ lists) {
+    __shared__ uint64_t s_buf[kBtPassThreads / kWave][2 * kWave];
     const int lane = threadIdx.x & (kWave - 1);
-    const int r = __builtin_amdgcn_readfirstlane(
-        rstart[first] + (int)blockIdx.x * (kBtPassThreads / kWave) + (int)threadIdx.x / kWave);
+    const int wid = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
+    const int r = rstart[first] + (int)blockIdx.x * (kBtPassThreads / kWave) + wid;
     const int rend = rstart[first + count - 1] + ns[perm[first + count - 1]];
     if (r >= rend) return;  // whole wave (r is wave-uniform); no barrier in this kernel
-    const int i = bt_find_graph(rstart, first, count, r);
+    const int i = rgraph[r];
     const int g = perm[i];
     const int n = ns[g];
     const int u = r - rstart[i];
     const float* row = W + offsets[g] + (size_t)u * n;
+    float x[E];
+    rank_row_load<E>(row, n, x);
     uint64_t mine;
-    if (!row_topk_compact<WIDEST, E, kBtK>(row, n, u, s_buf[threadIdx.x / kWave], &mine))
+    if (!row_topk_rank_vals<WIDEST, E, kBtK>(x, n, u, s_buf[wid], &mine))
         mine = row_topk<WIDEST, false, false, E, kBtK>(
             row, n, u, [](int) { return 0; }, [](int) { return make_int4(0, 0, 0, 0); });
     if (lane < kBtK) lists[(size_t)(noff[g] + u) * kBtK + lane] = mine;
@@ -553,7 +545,8 @@ hipError_t launch_btree_t(int c, int first, int count, int rows_in_class, const 
 #define APPD_BT_PASS(EE)                                                                    \
     APPD_LAUNCH("btree_pass_kernel", s,                                                     \
                 btree_pass_kernel<WIDEST, EE><<<blocks, kBtPassThreads, 0, s>>>(            \
-                    W, offsets, ns, plan.perm, plan.noff, plan.rstart, first, count, lists))
+                    W, offsets, ns, plan.perm, plan.noff, plan.rstart, plan.rgraph, first, count,  \
+                    lists))
     if (blocks > 0) {
         if (nmax <= 256) APPD_BT_PASS(4);
         else if (nmax <= 512) APPD_BT_PASS(8);

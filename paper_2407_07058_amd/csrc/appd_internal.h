@@ -85,6 +85,7 @@ struct BatchPlan {
     const int64_t* noff;         // [G] start of graph g's O(n) arrays (device, by graph id)
     const int32_t* chunk_start;  // [G] first fill item of perm[i] within its class (device)
     const int32_t* rstart;       // [G] sum of n over perm[0 .. i) (device)
+    const int32_t* rgraph;       // [total_n] i of row r, rows in perm order (device)
     uint64_t* lists;             // candidate lists of the Boruvka classes, K per vertex
     int32_t* tstats;             // [G] per graph, by graph id: how its tree was found
     int class_tree[kBatchClasses];

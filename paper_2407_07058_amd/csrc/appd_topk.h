@@ -7,6 +7,9 @@
 namespace appd {
 
 constexpr int kK = 16;  // candidate list length
+// Word 3 of a buffer resource on gfx9: 32-bit data format, no swizzle; with
+// stride 0 a load whose offset lies past the range returns 0.
+constexpr int kBufferRsrcWord3 = 0x00020000;
 constexpr uint64_t kTopkNone = ~0ull;
 
 // One wave per row.  Lanes 0..K-1 hold the row's K smallest entries seen so
@@ -131,97 +134,136 @@ __device__ __forceinline__ uint64_t row_topk(const float* __restrict__ row, int 
 }
 
 
-// The same KK smallest entries for a short row (n <= 64 * E, no column
-// filter) without inserting entries one at a time.  The threshold is taken as
-// above (at least KK lane minima, hence at least KK entries, lie at or below
-// it, so the KK smallest entries all do); every entry at or below it is
-// written to the wave's LDS buffer (a prefix sum over the lanes gives each
-// lane its place), one per lane is read back, and a bitonic sort across the
-// lanes orders them.  Returns false, leaving *out alone, when more than 64
-// entries lie at or below the threshold (then row_topk does the work).
-// wbuf: 64 entries of LDS owned by the calling wave.
-// The loads of a short row: column e * 64 + lane into x[e] (0 past the row).
-template <int E>
-__device__ __forceinline__ void short_row_load(const float* __restrict__ row, int n, float (&x)[E]) {
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int c = e * kWave + lane;
-        x[e] = c < n ? row[c] : 0.0f;
-    }
+// Set bits of a wave mask as a 32-bit count on the scalar unit (a count of a
+// 64-bit mask compared directly would be widened to a 64-bit vector compare).
+__device__ __forceinline__ int mask_count(uint64_t b) {
+    int r;
+    asm("s_bcnt1_i32_b64 %0, %1" : "=s"(r) : "s"(b));
+    return r;
 }
 
-// row_topk_compact on values already loaded by short_row_load.
+__device__ __forceinline__ int wave_count(bool p) { return mask_count(__ballot(p)); }
+
+// a where the lane's bit of the wave mask is set, else b (one select; written
+// out so that the operands are computed for every lane rather than under a
+// changed exec mask)
+__device__ __forceinline__ uint32_t select_by_mask(uint64_t mask, uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(mask));
+    return r;
+}
+
+// The loads of a short row (n <= 64 * E) for row_topk_rank_vals: column
+// e * 64 + lane into x[e], by buffer loads whose range is the row (loads past
+// it return 0 and touch no memory).
+template <int E>
+__device__ __forceinline__ void rank_row_load(const float* __restrict__ row, int n, float (&x)[E]) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float*>(row), (short)0, n * 4, kBufferRsrcWord3);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        x[e] = __builtin_bit_cast(
+            float, __builtin_amdgcn_raw_buffer_load_b32(rs, lane * 4 + e * (kWave * 4), 0, 0));
+}
+
+// The KK smallest entries of a short row u (n <= 64 * E, diagonal left out)
+// by one wave, from the values rank_row_load read: lane l < KK gets the l-th
+// smallest as ord32(s) << 32 | column (kTopkNone past the row's n - 1
+// entries), with no sort and few instructions per entry:
+//  - columns past n become NaN, which is never a candidate and which the lane
+//    minimum ignores;
+//  - the threshold is the (KK+1)-th smallest lane minimum, to 12 bits of the
+//    order key and rounded up, the diagonal taking part: one lane minimum may
+//    be the diagonal, so at least KK entries that are not lie at or below it;
+//  - each column block's candidates are a ballot; their count decides (more
+//    than 64: false, the caller falls back to row_topk); every lane writes its
+//    entry of each block to the wave's LDS buffer, a candidate at the block's
+//    base plus the candidates below it (mbcnt), any other lane to a slot of
+//    its own past the candidates' 64;
+//  - each candidate's rank is the number of smaller candidates (the diagonal
+//    dropped), counted against every candidate read back by broadcast, and
+//    the KK smallest are placed by rank.
+// wbuf: 128 entries of LDS owned by the calling wave.
 template <bool WIDEST, int E, int KK>
-__device__ __forceinline__ bool topk_compact_vals(const float (&xr)[E], int n, int u,
-                                                  uint64_t* wbuf, uint64_t* out) {
+__device__ __forceinline__ bool row_topk_rank_vals(const float (&xr)[E], int n, int u,
+                                                   uint64_t* wbuf, uint64_t* out) {
     static_assert(KK >= 1 && KK <= 16, "the list lives in lanes 0..15");
     constexpr uint64_t kNone = kTopkNone;
+    constexpr int kBits = 12;  // order-key bits the threshold search resolves
     const int lane = threadIdx.x & (kWave - 1);
     float sv[E];
-    bool skip[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) sv[e] = WIDEST ? -xr[e] : xr[e];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int c = e * kWave + lane;
-        sv[e] = WIDEST ? -xr[e] : xr[e];
-        skip[e] = c >= n || c == u;
+        const int rem = n - e * kWave;  // wave-uniform: only the last blocks take the branch
+        if (rem < kWave) {
+            asm volatile("");  // keeps the branch (no select for the whole blocks)
+            sv[e] = lane < rem ? sv[e] : __builtin_nanf("");
+        }
     }
     float lm = INFINITY;
 #pragma unroll
-    for (int e = 0; e < E; ++e) lm = fminf(lm, skip[e] ? INFINITY : sv[e]);
+    for (int e = 0; e < E; ++e) lm = fminf(lm, sv[e]);
     float thr = INFINITY;
-    if (__popcll(__ballot(lm < INFINITY)) >= KK) {
-        const uint32_t km = ord32(lm) >> 16;
+    if (wave_count(lm < INFINITY) > KK) {
+        const uint32_t km = ord32(lm) >> (32 - kBits);
         uint32_t res = 0;
-        for (int b = 15; b >= 0; --b) {
+#pragma unroll
+        for (int b = kBits - 1; b >= 0; --b) {
             const uint32_t c = res | (1u << b);
-            if (__popcll(__ballot(km < c)) < KK) res = c;
+            if (wave_count(km < c) <= KK) res = c;
         }
-        thr = res == 0xffffu ? INFINITY : ord32_inv((res << 16) | 0xffffu);
+        // res is the bucket of a finite lane minimum, so its top is a number
+        thr = ord32_inv((res << (32 - kBits)) | ((1u << (32 - kBits)) - 1));
     }
-    int cnt = 0;
-#pragma unroll
-    for (int e = 0; e < E; ++e) cnt += (!skip[e] && sv[e] <= thr) ? 1 : 0;
-    int incl = cnt;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int y = __shfl_up(incl, d);
-        if (lane >= d) incl += y;
-    }
-    const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
-    if (total > kWave) return false;
-    int off = incl - cnt;
+    uint64_t m[E];
+    int first[E];  // candidates before block e
+    int total = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        if (!skip[e] && sv[e] <= thr) {
-            wbuf[off] = ((uint64_t)ord32(sv[e]) << 32) | (uint32_t)(e * kWave + lane);
-            ++off;
-        }
+        m[e] = __ballot(sv[e] <= thr);
+        first[e] = total;
+        total += mask_count(m[e]);
+    }
+    if (total > kWave) return false;
+    // columns at wcol[slot], values at wcol[128 + slot]; slots 64 .. 127 are
+    // the other lanes' (one per lane).  The slot addresses are LDS (32-bit)
+    // addresses.
+    typedef __attribute__((address_space(3))) uint32_t lds_u32;
+    uint32_t* wcol = (uint32_t*)wbuf;
+    const uint32_t wbase = (uint32_t)(size_t)(lds_u32*)wcol;
+    const uint32_t dump = wbase + 4u * (kWave + lane);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m[e] >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m[e], 0u));
+        const uint32_t cb = __builtin_amdgcn_readfirstlane(wbase + 4u * (uint32_t)first[e]);
+        const uint32_t at = select_by_mask(m[e], cb + 4u * below, dump);
+        lds_u32* p = (lds_u32*)(size_t)at;
+        p[0] = (uint32_t)(e * kWave + lane);
+        p[2 * kWave] = __float_as_uint(sv[e]);
     }
     wave_lds_sync();
-    uint64_t x = lane < total ? wbuf[lane] : kNone;
-    wave_lds_sync();  // the buffer may be written again for the next row
-    // ascending bitonic sort of lanes 0 .. P-1 (P: a power of two >= total, >= 16)
-    int P = 16;
-    while (P < total) P <<= 1;
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const uint64_t y = shfl_xor_u64(x, stride);
-            const bool up = (lane & size) == 0;
-            const bool lower = (lane & stride) == 0;
-            x = (lower == up) ? umin64(x, y) : umax64(x, y);
-        }
+    uint64_t x = kNone;
+    if (lane < total) {
+        const uint32_t col = wcol[lane];
+        const uint32_t bits = wcol[2 * kWave + lane];
+        if ((int)col != u) x = ((uint64_t)ord32(__uint_as_float(bits)) << 32) | col;
     }
-    *out = lane < KK ? x : kNone;
+    const int valid = total - wave_count(lane < total && x == kNone);
+    wave_lds_sync();
+    if (lane < total) wbuf[lane] = x;
+    wave_lds_sync();
+    int rank = 0;
+    for (int j = 0; j < total; ++j) rank += wbuf[j] < x ? 1 : 0;
+    wave_lds_sync();
+    if (x != kNone && rank < KK) wbuf[rank] = x;
+    wave_lds_sync();
+    *out = lane < KK && lane < valid ? wbuf[lane] : kNone;
+    wave_lds_sync();  // the buffer may be written again for the next row
     return true;
-}
-
-template <bool WIDEST, int E, int KK>
-__device__ __forceinline__ bool row_topk_compact(const float* __restrict__ row, int n, int u,
-                                                 uint64_t* wbuf, uint64_t* out) {
-    float x[E];
-    short_row_load<E>(row, n, x);
-    return topk_compact_vals<WIDEST, E, KK>(x, n, u, wbuf, out);
 }
 
 }  // namespace appd

@@ -81,6 +81,34 @@ def test_batched_widest():
     check_batch(mixed_graphs(2)[:20], appd.WIDEST)
 
 
+def special_values_graphs(seed):
+    """Graphs whose rows stress the candidate selection of the batched tree
+    pass: signed zeros, negative weights, +inf and -inf entries (symmetric, a
+    diagonal of NaN, which the method never reads), long runs of one value,
+    and sizes on both sides of the 17-lane threshold rule."""
+    rng = np.random.default_rng(seed)
+    Ws = []
+    for k, n in enumerate([2, 5, 16, 17, 18, 40, 65, 130, 300, 700, 1024]):
+        W = rng.uniform(-1.0, 1.0, (n, n)).astype(np.float32)
+        r = rng.random((n, n))
+        W[r < 0.10] = np.inf
+        W[(r >= 0.10) & (r < 0.15)] = -np.inf
+        W[(r >= 0.15) & (r < 0.25)] = 0.0
+        W[(r >= 0.25) & (r < 0.35)] = -0.0
+        W[(r >= 0.35) & (r < 0.45)] = 0.5
+        W = np.triu(W, 1)
+        W = W + W.T
+        np.fill_diagonal(W, np.nan)
+        Ws.append(W)
+    return Ws
+
+
+def test_batched_special_values():
+    say("case batched special values (signed zeros, infinities, runs of ties)")
+    check_batch(special_values_graphs(11))
+    check_batch(special_values_graphs(12), appd.WIDEST)
+
+
 def test_batched_parent_matches_single():
     say("case batched parent vs single-graph tree")
     Ws = mixed_graphs(3)[:12]

@@ -51,7 +51,9 @@ enum appd_status {
     APPD_OK = 0,
     APPD_EINVAL = -1, /* null pointer, n out of range, workspace too small, bad mode */
     APPD_EHIP = -2,   /* a HIP runtime call or kernel launch failed */
-    APPD_ENOMEM = -3  /* a stream-ordered allocation failed */
+    APPD_ENOMEM = -3, /* a stream-ordered allocation failed */
+    APPD_EDATA = -4   /* reported by appd_sync: a forward run with APPD_VALIDATE set
+                         read a W with a NaN entry or an asymmetric pair */
 };
 
 enum appd_mode {
@@ -92,6 +94,23 @@ int appd_get_last_error(void);
 #define APPD_VALID_ASYM 0x2u
 #define APPD_VALID_DIAG 0x4u
 int appd_validate(const float* W, int n, uint32_t* flags, void* stream);
+
+/*
+ * Waits for `stream` and reports what went wrong asynchronously on it, as the
+ * return value and as appd_get_last_error() of the calling thread:
+ *   APPD_EHIP   the stream reported a HIP error (a failed kernel);
+ *   APPD_EDATA  a single-graph forward (appd_forward / _ws / _ex / _noalloc)
+ *               enqueued while the environment variable APPD_VALIDATE was set
+ *               (to anything but "0") read a W with a NaN entry or an
+ *               asymmetric pair (the checks of appd_validate, enqueued before
+ *               the forward's kernels; a non-zero diagonal is not an error,
+ *               the forward never reads it).  The record is per GPU and is
+ *               cleared by the call that reports it;
+ *   APPD_OK     otherwise.
+ * Not for use under stream capture (it synchronises).  Environment variable
+ * APPD_LOG (anything but "0"): every kernel launch is written to stderr.
+ */
+int appd_sync(void* stream);
 
 /* Bytes of device workspace appd_forward_ws / appd_forward_ex need for n
  * (0 if n is out of range). */

@@ -67,6 +67,10 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
+    other = os.environ.get("APPD_ORACLE_LIB")  # another build (the sanitizer test's)
+    if other:
+        _lib = _bind(other)
+        return _lib
     if not os.path.exists(_LIB):
         build()
     _lib = _bind(_LIB)

@@ -18,7 +18,9 @@ import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libappd.so")
+# APPD_LIB names another build of the same library (the sanitizer test loads a
+# host-instrumented one); by default the in-tree build.
+LIB_PATH = os.environ.get("APPD_LIB") or os.path.join(_PKG, "libappd.so")
 
 MINIMAX = 0
 WIDEST = 1
@@ -31,6 +33,7 @@ APPD_OK = 0
 APPD_EINVAL = -1
 APPD_EHIP = -2
 APPD_ENOMEM = -3
+APPD_EDATA = -4
 
 # every symbol include/appd.h declares, with its ctypes signature
 _P = ctypes.c_void_p
@@ -39,6 +42,7 @@ _SZ = ctypes.c_size_t
 SIGNATURES = {
     "appd_error_string": ([_I], ctypes.c_char_p),
     "appd_validate": ([_P, _I, _P, _P], _I),
+    "appd_sync": ([_P], _I),
     "appd_get_last_error": ([], _I),
     "appd_forward_workspace_bytes": ([_I], _SZ),
     "appd_forward": ([_P, _I, _P, _P, _P], _I),
@@ -195,6 +199,15 @@ def validate(W: torch.Tensor) -> int:
     flags = torch.empty(1, dtype=torch.int32, device=W.device)
     _check(lib().appd_validate(_ptr(W), n, _ptr(flags), _stream(W.device)), "appd_validate")
     return int(flags.item()) & 0xffffffff
+
+
+def sync(device=None) -> None:
+    """Wait for the device's current stream and raise APPDError for what went
+    wrong on it asynchronously (appd_sync): a failed kernel, or a forward
+    enqueued with APPD_VALIDATE set that read a W with a NaN or an asymmetric
+    pair."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    _check(lib().appd_sync(_stream(dev)), "appd_sync")
 
 
 def _mode(mode: int, tree: str) -> int:

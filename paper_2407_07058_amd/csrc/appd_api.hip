@@ -34,6 +34,7 @@ const char* appd_error_string(int code) {
         case APPD_EINVAL: return "APPD_EINVAL: invalid argument (null pointer, n out of range, workspace too small or bad mode)";
         case APPD_EHIP: return "APPD_EHIP: HIP runtime call or kernel launch failed";
         case APPD_ENOMEM: return "APPD_ENOMEM: device allocation failed";
+        case APPD_EDATA: return "APPD_EDATA: a validated forward read a W with a NaN or an asymmetric pair";
         default: return "unknown appd status code";
     }
 }
@@ -63,7 +64,8 @@ int appd_forward_ex(const float* W, int n, int mode, float* M, int32_t* idx, int
     appd::SingleWs w = appd::carve_single(buf, n);
     if (order) w.order = order;
     if (parent) w.parent = parent;
-    hipError_t e = appd::run_single(W, n, mode, M, idx, w, s);
+    hipError_t e = appd::validate_requested() ? appd::enqueue_input_check(W, n, s) : hipSuccess;
+    if (e == hipSuccess) e = appd::run_single(W, n, mode, M, idx, w, s);
     if (!ws) {
         if (hipFreeAsync(buf, s) != hipSuccess && e == hipSuccess) e = hipErrorUnknown;
     }

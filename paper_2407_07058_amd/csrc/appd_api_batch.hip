@@ -48,11 +48,11 @@ struct Tables {
 
 Tables carve(void* ws, int G, int64_t total_n) {
     using appd::align_up;
-    char* b = (char*)ws;
+    const uintptr_t b = (uintptr_t)ws;  // null when only the size is wanted
     Tables t;
     size_t off = 0;
     auto take = [&](size_t bytes) {
-        char* p = b + off;
+        char* p = (char*)(b + off);
         off = align_up(off + bytes);
         return p;
     };

@@ -14,8 +14,20 @@ void set_last_error(int code);
 bool timer_wants(const char* name);
 void timer_begin(const char* name, hipStream_t s);
 void timer_end(hipStream_t s);
+
+// Launch log (environment variable APPD_LOG, read once): one stderr line per
+// kernel launch.
+bool log_on();
+void log_launch(const char* name, hipStream_t s);
+
+// Input checks of the single-graph forward (environment variable
+// APPD_VALIDATE, read at each call): the validation pass or-s its flags into a
+// per-GPU record that appd_sync reports and clears.
+bool validate_requested();
+hipError_t enqueue_input_check(const float* W, int n, hipStream_t s);
 #define APPD_LAUNCH(name, stream, ...)                        \
     do {                                                      \
+        if (::appd::log_on()) ::appd::log_launch(name, (stream)); \
         const bool appd_timed_ = ::appd::timer_wants(name);   \
         if (appd_timed_) ::appd::timer_begin(name, (stream)); \
         __VA_ARGS__;                                          \

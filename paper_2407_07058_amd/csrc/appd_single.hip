@@ -108,7 +108,7 @@ size_t single_workspace_bytes(int n) {
 
 SingleWs carve_single(void* ws, int n) {
     const size_t nb = (size_t)fill_blocks(n) * kFillCB;
-    char* b = (char*)ws;
+    const uintptr_t b = (uintptr_t)ws;  // null when only the size is wanted
     SingleWs w;
     size_t off = 0;
     w.order = (int32_t*)(b + off);
@@ -131,7 +131,7 @@ SingleWs carve_single(void* ws, int n) {
     off = align_up(off + 4 * nb);
     w.blk_sorted = (uint64_t*)(b + off);
     off = align_up(off + 8 * nb);
-    w.tree_ws = b + off;
+    w.tree_ws = (void*)(b + off);
     return w;
 }
 

@@ -2,6 +2,8 @@
 // stream immediately before and after each launch of the selected kernel(s).
 // The events are created by appd_timer_start, so a timed region records events
 // only; nothing is allocated while it runs.
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <atomic>
@@ -36,6 +38,25 @@ void destroy_pool() {
     g_next = 0;
 }
 
+int env_flag(const char* name) {
+    const char* v = getenv(name);
+    return (v && *v && strcmp(v, "0") != 0) ? 1 : 0;
+}
+
+}  // namespace
+
+bool log_on() {
+    static const bool on = env_flag("APPD_LOG") != 0;
+    return on;
+}
+
+void log_launch(const char* name, hipStream_t s) {
+    fprintf(stderr, "appd: launch %s stream=%p\n", name, (void*)s);
+}
+
+bool validate_requested() { return env_flag("APPD_VALIDATE") != 0; }
+
+namespace {
 }  // namespace
 
 bool timer_wants(const char* name) {

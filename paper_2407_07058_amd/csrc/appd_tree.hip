@@ -1376,10 +1376,10 @@ struct TreeWs {
 // Order-phase arrays reuse the list storage (the lists are dead by then):
 // six int arrays of n fit in the 8 * K * n bytes.
 static TreeWs carve_tree(void* ws, int n) {
-    char* b = (char*)ws;
+    const uintptr_t b = (uintptr_t)ws;  // null when only the size is wanted
     size_t off = 0;
     auto take = [&](size_t bytes) {
-        char* p = b + off;
+        char* p = (char*)(b + off);
         off = align_up(off + bytes);
         return p;
     };
@@ -1393,13 +1393,13 @@ static TreeWs carve_tree(void* ws, int n) {
     w.ctrl = (int32_t*)take(4 * 64);
     w.cmpart = (uint64_t*)take(8 * (size_t)kCmat * kCmat * kCmatBlocks(n));
     w.bytes = off;
-    int32_t* r = (int32_t*)w.lists;
-    w.tstart = r;
-    w.grouped = r + n;
-    w.rank = r + 2 * (size_t)n;
-    w.sorted_size = r + 3 * (size_t)n;
-    w.sorted_grp = r + 4 * (size_t)n;
-    w.sorted_pre = r + 5 * (size_t)n;
+    const uintptr_t r = (uintptr_t)w.lists;
+    w.tstart = (int32_t*)r;
+    w.grouped = (int32_t*)(r + 4 * (size_t)n);
+    w.rank = (int32_t*)(r + 8 * (size_t)n);
+    w.sorted_size = (int32_t*)(r + 12 * (size_t)n);
+    w.sorted_grp = (int32_t*)(r + 16 * (size_t)n);
+    w.sorted_pre = (int32_t*)(r + 20 * (size_t)n);
     return w;
 }
 

@@ -7,6 +7,8 @@
 // coalesced, the second through LDS transposed), so every element is read
 // once and compared with its mirror image.  Flags are or-ed per wave into one
 // device word.
+#include <mutex>
+
 #include "appd.h"
 #include "appd_device.h"
 #include "appd_internal.h"
@@ -74,8 +76,67 @@ __global__ void validate_clear_kernel(uint32_t* flags) {
     if (threadIdx.x == 0) *flags = 0u;
 }
 
+// Flags of the validated forwards since the last appd_sync on this GPU.
+__device__ uint32_t pending_flags;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_pending_mu;
+uint32_t* g_pending_ptr[kMaxDevices];
+
+// The current GPU's copy of pending_flags (null on a HIP error).
+uint32_t* pending_for_current_device() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_pending_mu);
+    if (!g_pending_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(pending_flags)) != hipSuccess || !p) return nullptr;
+        g_pending_ptr[dev] = (uint32_t*)p;
+    }
+    return g_pending_ptr[dev];
+}
+
 }  // namespace
+
+hipError_t enqueue_input_check(const float* W, int n, hipStream_t s) {
+    uint32_t* pending = pending_for_current_device();
+    if (!pending) return hipErrorUnknown;
+    const int T = (n + kVT - 1) / kVT;
+    APPD_LAUNCH("validate_kernel", s,
+                validate_kernel<<<T * (T + 1) / 2, kVThreads, 0, s>>>(W, n, T, pending));
+    return hipGetLastError();
+}
+
 }  // namespace appd
+
+extern "C" int appd_sync(void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        appd::set_last_error(APPD_EHIP);
+        return APPD_EHIP;
+    }
+    uint32_t* pending = appd::pending_for_current_device();
+    uint32_t flags = 0;
+    if (!pending || hipMemcpyAsync(&flags, pending, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        appd::set_last_error(APPD_EHIP);
+        return APPD_EHIP;
+    }
+    if (flags) {
+        const uint32_t zero = 0;
+        if (hipMemcpyAsync(pending, &zero, 4, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            (void)hipGetLastError();
+            appd::set_last_error(APPD_EHIP);
+            return APPD_EHIP;
+        }
+    }
+    const int rc = (flags & (APPD_VALID_NAN | APPD_VALID_ASYM)) ? APPD_EDATA : APPD_OK;
+    appd::set_last_error(rc);
+    return rc;
+}
 
 extern "C" int appd_validate(const float* W, int n, uint32_t* flags, void* stream) {
     if (!W || !flags || n < 1 || n > APPD_MAX_N) {

@@ -38,8 +38,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_error_strings():
     L = appd.lib()
-    for c in (0, -1, -2, -3):
+    for c in (0, -1, -2, -3, -4):
         assert L.appd_error_string(c)
+        assert b"unknown" not in L.appd_error_string(c)
     assert b"unknown" in L.appd_error_string(7)
 
 
@@ -174,3 +175,24 @@ def test_backward_w_batched_rejects_bad_arguments():
                                      None) == appd.APPD_EINVAL
     assert L.appd_backward_w_batched(None, P(256), P(256), P(256), ctypes.byref(plan), P(256),
                                      None) == appd.APPD_EINVAL
+
+
+def test_batch_prepare_host_tables_without_a_device():
+    """The host half of appd_batch_prepare (size classes, the n-descending
+    order, work tables, the per-row graph table) runs to its first device copy,
+    which fails when no GPU is present (APPD_EHIP).  Run under the sanitizer
+    test, this checks the table construction's memory accesses."""
+    import numpy as np
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present: the copy to a made-up workspace would reach it")
+    L = appd.lib()
+    P = ctypes.c_void_p
+    rng = np.random.default_rng(5)
+    ns = rng.integers(1, 2049, 300).astype(np.int32)
+    need = L.appd_batch_workspace_bytes(ns.ctypes.data_as(P), len(ns))
+    assert need > 0
+    plan = appd.BatchPlan()
+    rc = L.appd_batch_prepare(ns.ctypes.data_as(P), len(ns), P(1 << 20), need, ctypes.byref(plan),
+                              None)
+    assert rc == appd.APPD_EHIP

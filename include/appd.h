@@ -98,7 +98,9 @@ int appd_validate(const float* W, int n, uint32_t* flags, void* stream);
 /*
  * Waits for `stream` and reports what went wrong asynchronously on it, as the
  * return value and as appd_get_last_error() of the calling thread:
- *   APPD_EHIP   the stream reported a HIP error (a failed kernel);
+ *   APPD_EHIP   the stream reported a HIP error (a failed kernel), or a wait of
+ *               the persistent batched forward gave up (its outputs are then
+ *               incomplete);
  *   APPD_EDATA  a single-graph forward (appd_forward / _ws / _ex / _noalloc)
  *               enqueued while the environment variable APPD_VALIDATE was set
  *               (to anything but "0") read a W with a NaN entry or an
@@ -252,6 +254,10 @@ typedef struct {
     int class_vertices[APPD_BATCH_CLASSES]; /* sum of n over the class's graphs */
     int split_vertices; /* sum of n over the graphs launched on their own (set with
                            split_count) */
+    int persistent;     /* 1: the whole forward as one persistent launch over a work queue
+                           (every class APPD_BATCH_TREE_BORUVKA, every n <= 1024); 0: one
+                           launch sequence per class */
+    int persist_items;  /* work items of that launch (set with persistent) */
 } appd_batch_plan;
 
 /* class_tree values.  Prim: one workgroup per graph runs Prim's algorithm

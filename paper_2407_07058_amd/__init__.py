@@ -100,7 +100,9 @@ class BatchPlan(ctypes.Structure):
                 ("split_chunks", ctypes.c_int), ("tables_key", ctypes.c_uint64),
                 ("class_tree", ctypes.c_int * BATCH_CLASSES),
                 ("class_vertices", ctypes.c_int * BATCH_CLASSES),
-                ("split_vertices", ctypes.c_int)]
+                ("split_vertices", ctypes.c_int),
+                ("persistent", ctypes.c_int),
+                ("persist_items", ctypes.c_int)]
 
 _lib = None
 
@@ -323,8 +325,11 @@ class Batch:
                "appd_batch_prepare")
 
     def autotune(self, W: torch.Tensor, out=None) -> float:
-        """Time the candidate schedules on this batch's W and keep the fastest;
-        returns its milliseconds per forward.  Synchronises; not capturable."""
+        """Time the candidate schedules on this batch's W (median of 5 forwards
+        each) and keep the fastest; returns its milliseconds per forward.  With
+        APPD_TUNE_CACHE naming a JSON file, a schedule kept there for this GPU
+        and class histogram is taken without timing, and a new one is stored.
+        Synchronises; not capturable."""
         _check_tensor(W, "W", torch.float32, self.total_nn, self.device)
         M, idx = _check_out(out, self.total_nn, self.device)
         ms = ctypes.c_float()
@@ -333,10 +338,13 @@ class Batch:
                "appd_batch_autotune")
         return ms.value
 
-    def set_schedule(self, threads=None, rows=None, streams=None, split_count=None, trees=None):
+    def set_schedule(self, threads=None, rows=None, streams=None, split_count=None, trees=None,
+                     persistent=None):
         """Set the schedule by hand (Prim workgroup size and fill rows per item of
         each class, streams, and how many of the largest class's biggest graphs
-        run on their own); rebuilds the device work tables.  Synchronises."""
+        run on their own, -1 for a cut into halves of equal work; persistent:
+        the whole forward as one launch over a work queue); rebuilds the device
+        work tables.  Synchronises."""
         p = self.plan
         for c in range(BATCH_CLASSES):
             if threads is not None:
@@ -350,6 +358,8 @@ class Batch:
             p.streams = int(streams)
         if split_count is not None:
             p.split_count = int(split_count)
+        if persistent is not None:
+            p.persistent = int(bool(persistent))
         _check(lib().appd_batch_set_schedule(ctypes.byref(p), _ptr(self.ws), _stream(self.device)),
                "appd_batch_set_schedule")
 
@@ -376,7 +386,8 @@ class Batch:
         return {"class_count": list(p.class_count), "class_threads": list(p.class_threads),
                 "class_rows": list(p.class_rows), "streams": p.streams,
                 "split_count": p.split_count,
-                "class_tree": [names.get(x, x) for x in p.class_tree]}
+                "class_tree": [names.get(x, x) for x in p.class_tree],
+                "persistent": int(p.persistent)}
 
     def forward(self, W: torch.Tensor, mode: int = MINIMAX, return_parent: bool = False,
                 out=None):

@@ -12,7 +12,7 @@ LIB = os.path.join(PKG, "libappd.so")
 SOURCES = ["appd_api.hip", "appd_api_batch.hip", "appd_single.hip", "appd_batched.hip", "appd_grad.hip", "appd_tree.hip",
            "appd_timer.hip", "appd_validate.hip",
            "appd_noalloc.hip", "appd_membench.hip",
-           "appd_btree.hip"]
+           "appd_btree.hip", "appd_persist.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,8 +1,13 @@
 // C ABI of the batched and gradient calls (include/appd.h): host planning,
 // workspace carving, argument checks.  All compute runs in the kernels.
+#include <stdio.h>
+#include <stdlib.h>
+#include <unistd.h>
+
 #include <algorithm>
 #include <cstring>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "appd.h"
@@ -42,9 +47,17 @@ struct Tables {
     appd::BatchBlk blk;
     uint64_t* lists;
     int32_t* tstats;
+    uint2* items;  // work queue of the persistent form
+    int* ctr;      // its counters
     size_t table_bytes;  // bytes of the region uploaded by prepare
     size_t total_bytes;
 };
+
+// Work items of the persistent form, at most: one pass item per
+// kPersistThreads / 64 rows, one tree item per graph, one fill item per row.
+size_t items_capacity(int G, int64_t total_n) {
+    return (size_t)total_n + (size_t)(total_n + 7) / 8 + (size_t)G + 2;
+}
 
 Tables carve(void* ws, int G, int64_t total_n) {
     using appd::align_up;
@@ -81,6 +94,8 @@ Tables carve(void* ws, int G, int64_t total_n) {
     t.blk.sorted = (uint64_t*)take(8 * (size_t)total_n);
     t.lists = (uint64_t*)take(8 * 16 * (size_t)total_n);
     t.tstats = (int32_t*)take(4 * (size_t)G);
+    t.items = (uint2*)take(8 * items_capacity(G, total_n));
+    t.ctr = (int*)take(4 * (2 + 2 * (size_t)G));
     t.total_bytes = off;
     return t;
 }
@@ -122,6 +137,12 @@ appd::BatchPlan device_plan(const appd_batch_plan* p, const Tables& t) {
     bp.split_count = p->split_count;
     bp.split_chunks = p->split_chunks;
     bp.split_vertices = p->split_vertices;
+    bp.persistent = p->persistent;
+    bp.persist_items = p->persist_items;
+    bp.num_graphs = p->num_graphs;
+    bp.total_n = (int)p->total_n;
+    bp.items = t.items;
+    bp.ctr = t.ctr;
     return bp;
 }
 
@@ -149,7 +170,19 @@ uint64_t tables_key_of(const appd_batch_plan* p) {
     mix(p->split_count);
     mix(p->split_chunks);
     mix(p->split_vertices);
+    mix(p->persistent);
+    mix(p->persist_items);
     return h;
+}
+
+// The persistent form takes Boruvka classes of n <= kPersistMaxN only.
+bool persistent_ok(const appd_batch_plan* p) {
+    for (int c = 0; c < appd::kBatchClasses; ++c) {
+        if (!p->class_count[c]) continue;
+        if (appd::kClassMaxN[c] > appd::kPersistMaxN) return false;
+        if (p->class_tree[c] != APPD_BATCH_TREE_BORUVKA) return false;
+    }
+    return true;
 }
 
 bool schedule_ok(const appd_batch_plan* p) {
@@ -170,6 +203,11 @@ bool schedule_ok(const appd_batch_plan* p) {
         if (p->class_tree[c] != APPD_BATCH_TREE_PRIM && p->class_tree[c] != APPD_BATCH_TREE_BORUVKA)
             return false;
     }
+    if (p->persistent != 0 && p->persistent != 1) return false;
+    if (p->persistent && !persistent_ok(p)) return false;
+    if (p->persistent &&
+        (p->persist_items < 1 || (size_t)p->persist_items > items_capacity(p->num_graphs, p->total_n)))
+        return false;
     return true;
 }
 
@@ -184,7 +222,7 @@ bool schedule_ok(const appd_batch_plan* p) {
 // first h graphs.  Sets class_chunks, split_count, split_chunks, split_vertices
 // and the tables' stamp.
 void build_chunks(const int32_t* ns_host, const std::vector<int32_t>& perm, appd_batch_plan* p,
-                  std::vector<int32_t>& chunk_start, int split) {
+                  std::vector<int32_t>& chunk_start, int split, std::vector<uint2>* items) {
     const int G = p->num_graphs;
     chunk_start.assign(G, 0);
     for (int c = 0; c < appd::kBatchClasses; ++c) p->class_chunks[c] = 0;
@@ -222,7 +260,43 @@ void build_chunks(const int32_t* ns_host, const std::vector<int32_t>& perm, appd
             for (int i = 0; i < h; ++i) p->split_vertices += ns_host[perm[first + i]];
         }
     }
+    p->persist_items = 0;
+    if (items) items->clear();
+    if (p->persistent && items) {
+        // pass items over the rows in perm order, each graph's tree item after
+        // the pass item holding its last row; then the fill items, largest
+        // graphs first
+        constexpr int NW = appd::kPersistThreads / 64;  // one row per wave
+        const int64_t total = p->total_n;
+        int gi = 0;
+        int64_t gend = ns_host[perm[0]];
+        for (int64_t r = 0; r < total; r += NW) {
+            items->push_back(make_uint2(appd::kItemPass << 30 | (uint32_t)r, 0u));
+            const int64_t rend = std::min<int64_t>(total, r + NW);
+            while (gi < G && gend <= rend) {
+                items->push_back(make_uint2(appd::kItemTree << 30 | (uint32_t)gi, 0u));
+                if (++gi < G) gend += ns_host[perm[gi]];
+            }
+        }
+        for (int i = 0; i < G; ++i) {
+            const int n = ns_host[perm[i]];
+            const int rows = p->class_rows[appd::batch_class_of(n)];
+            for (int r0 = 0; r0 < n; r0 += rows)
+                items->push_back(make_uint2(appd::kItemFill << 30 | (uint32_t)i,
+                                            (uint32_t)r0 | (uint32_t)std::min(rows, n - r0) << 16));
+        }
+        p->persist_items = (int)items->size();
+    }
     p->tables_key = tables_key_of(p);
+}
+
+// Uploads what build_chunks made (synchronous copies).
+hipError_t upload_schedule(const Tables& t, int G, const std::vector<int32_t>& chunk_start,
+                           const std::vector<uint2>& items) {
+    hipError_t e = hipMemcpy(t.chunk_start, chunk_start.data(), 4 * (size_t)G, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !items.empty())
+        e = hipMemcpy(t.items, items.data(), 8 * items.size(), hipMemcpyHostToDevice);
+    return e;
 }
 
 // Default schedule: Boruvka trees for every class (Prim workgroups, when a
@@ -242,6 +316,164 @@ int hip_status(hipError_t e) {
     if (e == hipSuccess) return ok();
     (void)hipGetLastError();
     return fail(APPD_EHIP);
+}
+
+// ---- autotuner: candidate schedules and the plan cache
+
+constexpr int kTuneReps = 5;  // timed forwards per candidate (the median counts)
+
+// What a schedule sets (split: the cut argument of build_chunks, 0 or -1).
+struct TuneEntry {
+    int streams = 1, split = 0, persistent = 0;
+    int rows[appd::kBatchClasses] = {};
+    int tree[appd::kBatchClasses] = {};
+    int threads[appd::kBatchClasses] = {};
+    float ms = -1.f;
+};
+
+TuneEntry entry_of(const appd_batch_plan* p) {
+    TuneEntry e;
+    e.streams = p->streams;
+    e.split = p->split_count ? -1 : 0;
+    e.persistent = p->persistent;
+    for (int c = 0; c < appd::kBatchClasses; ++c) {
+        e.rows[c] = p->class_rows[c];
+        e.tree[c] = p->class_tree[c];
+        e.threads[c] = p->class_threads[c];
+    }
+    return e;
+}
+
+void apply_entry(const TuneEntry& e, appd_batch_plan* p) {
+    p->streams = e.streams;
+    p->persistent = e.persistent;
+    for (int c = 0; c < appd::kBatchClasses; ++c) {
+        p->class_rows[c] = e.rows[c];
+        p->class_tree[c] = e.tree[c];
+        p->class_threads[c] = e.threads[c];
+    }
+}
+
+// Cache key: the device (architecture and name) and the batch's class
+// histogram (graphs per size class).
+std::string tune_key(const appd_batch_plan* p) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return std::string();
+    }
+    std::string k = std::string(prop.gcnArchName) + "|" + prop.name + "|classes";
+    for (int c = 0; c < appd::kBatchClasses; ++c) k += ":" + std::to_string(p->class_count[c]);
+    for (char& ch : k)
+        if (ch == '"' || ch == '\\' || (unsigned char)ch < 0x20) ch = '_';
+    return k;
+}
+
+// The cache file is one JSON object, one entry per line:
+//   "key": {"streams": 3, "split": -1, "persistent": 0, "rows": [...6],
+//           "trees": [...6], "threads": [...6], "ms": 1.234}
+std::string entry_line(const std::string& key, const TuneEntry& e) {
+    char buf[512];
+    std::string r = "\"" + key + "\": {";
+    snprintf(buf, sizeof buf, "\"streams\": %d, \"split\": %d, \"persistent\": %d", e.streams, e.split,
+             e.persistent);
+    r += buf;
+    const int* arr[3] = {e.rows, e.tree, e.threads};
+    const char* names[3] = {"rows", "trees", "threads"};
+    for (int a = 0; a < 3; ++a) {
+        r += std::string(", \"") + names[a] + "\": [";
+        for (int c = 0; c < appd::kBatchClasses; ++c) r += (c ? ", " : "") + std::to_string(arr[a][c]);
+        r += "]";
+    }
+    snprintf(buf, sizeof buf, ", \"ms\": %.4f}", e.ms);
+    return r + buf;
+}
+
+bool parse_entry(const std::string& line, std::string* key, TuneEntry* e) {
+    const size_t q0 = line.find('"');
+    const size_t q1 = q0 == std::string::npos ? q0 : line.find('"', q0 + 1);
+    if (q1 == std::string::npos) return false;
+    *key = line.substr(q0 + 1, q1 - q0 - 1);
+    const char* s = line.c_str() + q1 + 1;
+    int v[3 + 3 * appd::kBatchClasses];
+    float ms = 0.f;
+    int used = 0;
+    if (sscanf(s, ": {\"streams\": %d, \"split\": %d, \"persistent\": %d%n", &v[0], &v[1], &v[2],
+               &used) != 3)
+        return false;
+    s += used;
+    const char* names[3] = {"rows", "trees", "threads"};
+    for (int a = 0; a < 3; ++a) {
+        const std::string head = std::string(", \"") + names[a] + "\": [";
+        if (strncmp(s, head.c_str(), head.size()) != 0) return false;
+        s += head.size();
+        for (int c = 0; c < appd::kBatchClasses; ++c) {
+            if (sscanf(s, c ? ", %d%n" : "%d%n", &v[3 + a * appd::kBatchClasses + c], &used) != 1)
+                return false;
+            s += used;
+        }
+        if (*s++ != ']') return false;
+    }
+    if (sscanf(s, ", \"ms\": %f", &ms) != 1) return false;
+    e->streams = v[0];
+    e->split = v[1];
+    e->persistent = v[2];
+    for (int c = 0; c < appd::kBatchClasses; ++c) {
+        e->rows[c] = v[3 + c];
+        e->tree[c] = v[3 + appd::kBatchClasses + c];
+        e->threads[c] = v[3 + 2 * appd::kBatchClasses + c];
+    }
+    e->ms = ms;
+    return true;
+}
+
+std::vector<std::string> read_lines(const char* path) {
+    std::vector<std::string> out;
+    FILE* f = fopen(path, "r");
+    if (!f) return out;
+    char buf[4096];
+    while (fgets(buf, sizeof buf, f)) {
+        std::string l(buf);
+        while (!l.empty() && (l.back() == '\n' || l.back() == '\r' || l.back() == ',')) l.pop_back();
+        if (!l.empty() && l[0] == '"') out.push_back(l);
+    }
+    fclose(f);
+    return out;
+}
+
+bool cache_lookup(const char* path, const std::string& key, TuneEntry* e) {
+    for (const std::string& l : read_lines(path)) {
+        std::string k;
+        TuneEntry x;
+        if (parse_entry(l, &k, &x) && k == key) {
+            *e = x;
+            return true;
+        }
+    }
+    return false;
+}
+
+// Replaces or adds the key's entry; the file is written beside and renamed
+// over the old one, so a reader never sees half a file.
+void cache_store(const char* path, const std::string& key, const TuneEntry& e) {
+    std::vector<std::string> lines;
+    for (const std::string& l : read_lines(path)) {
+        std::string k;
+        TuneEntry x;
+        if (parse_entry(l, &k, &x) && k != key) lines.push_back(l);
+    }
+    lines.push_back(entry_line(key, e));
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long)getpid());
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fputs("{\n", f);
+    for (size_t i = 0; i < lines.size(); ++i)
+        fprintf(f, "%s%s\n", lines[i].c_str(), i + 1 < lines.size() ? "," : "");
+    fputs("}\n", f);
+    const bool good = fclose(f) == 0;
+    if (good) rename(tmp.c_str(), path);
+    else remove(tmp.c_str());
 }
 
 }  // namespace
@@ -312,7 +544,8 @@ int appd_batch_prepare(const int32_t* ns_host, int num_graphs, void* ws, size_t 
     for (int c = 0; c < appd::kBatchClasses; ++c)
         if (p.class_first[c] < 0) p.class_first[c] = 0;
     default_schedule(&p);
-    build_chunks(ns_host, perm, &p, chunk_start, 0);
+    std::vector<uint2> items;
+    build_chunks(ns_host, perm, &p, chunk_start, 0, &items);
 
     // one host image of the table region, one synchronous copy
     std::vector<char> img(lay.table_bytes, 0);
@@ -330,7 +563,8 @@ int appd_batch_prepare(const int32_t* ns_host, int num_graphs, void* ws, size_t 
         std::fill(h.rgraph + rstart[i], h.rgraph + rstart[i] + ns_host[perm[i]], (int32_t)i);
     hipStream_t s = (hipStream_t)stream;
     if (hipMemcpyAsync(ws, img.data(), lay.table_bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
+        hipStreamSynchronize(s) != hipSuccess ||
+        (!items.empty() && upload_schedule(carve(ws, G, tn), G, chunk_start, items) != hipSuccess)) {
         (void)hipGetLastError();
         return fail(APPD_EHIP);
     }
@@ -345,80 +579,139 @@ int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan*
     const int G = plan->num_graphs;
     Tables t = carve(ws, G, plan->total_n);
     std::vector<int32_t> ns(G), perm(G), chunk_start;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    auto hip_fail = [&](hipError_t e) {
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
+    std::vector<uint2> items;
+    hipEvent_t ev[kTuneReps + 1] = {};
+    auto hip_fail = [&]() {
+        for (hipEvent_t x : ev)
+            if (x) (void)hipEventDestroy(x);
         (void)hipGetLastError();
-        (void)e;
         return fail(APPD_EHIP);
     };
-    hipError_t e;
-    if ((e = hipStreamSynchronize(s)) != hipSuccess ||
-        (e = hipMemcpy(ns.data(), t.ns, 4 * (size_t)G, hipMemcpyDeviceToHost)) != hipSuccess ||
-        (e = hipMemcpy(perm.data(), t.perm, 4 * (size_t)G, hipMemcpyDeviceToHost)) != hipSuccess ||
-        (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
-        return hip_fail(e);
-    // candidates: Prim workgroup sizes (narrow / wide), fill rows per item,
-    // classes in order or on concurrent streams
+    if (hipStreamSynchronize(s) != hipSuccess ||
+        hipMemcpy(ns.data(), t.ns, 4 * (size_t)G, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(perm.data(), t.perm, 4 * (size_t)G, hipMemcpyDeviceToHost) != hipSuccess)
+        return hip_fail();
+    // a schedule from the plan cache, when one is kept for this device and
+    // class histogram
+    const char* cache = getenv("APPD_TUNE_CACHE");
+    const std::string key = tune_key(plan);
+    TuneEntry hit;
+    if (cache && *cache && !key.empty() && cache_lookup(cache, key, &hit)) {
+        appd_batch_plan p = *plan;
+        apply_entry(hit, &p);
+        build_chunks(ns.data(), perm, &p, chunk_start, hit.split, &items);
+        if (schedule_ok(&p) && upload_schedule(t, G, chunk_start, items) == hipSuccess) {
+            *plan = p;
+            if (best_ms) *best_ms = hit.ms;
+            return ok();
+        }
+    }
+    for (hipEvent_t& x : ev)
+        if (hipEventCreate(&x) != hipSuccess) return hip_fail();
+    // time of one candidate: the median over kTuneReps forwards after one
+    // warm-up forward (split: the cut argument of build_chunks)
+    auto measure = [&](appd_batch_plan* p, int split, float* ms) -> bool {
+        build_chunks(ns.data(), perm, p, chunk_start, split, &items);
+        if (!schedule_ok(p)) return false;
+        if (hipStreamSynchronize(s) != hipSuccess || upload_schedule(t, G, chunk_start, items) != hipSuccess)
+            return false;
+        appd::BatchTree tree{t.order, t.ek, t.pos, t.parent};
+        const appd::BatchPlan bp = device_plan(p, t);
+        if (appd::run_batched(W, t.offsets, t.ns, bp, tree, t.blk, APPD_MINIMAX, M, idx, s) != hipSuccess)
+            return false;
+        for (int r = 0; r < kTuneReps; ++r) {
+            if (hipEventRecord(ev[r], s) != hipSuccess ||
+                appd::run_batched(W, t.offsets, t.ns, bp, tree, t.blk, APPD_MINIMAX, M, idx, s) != hipSuccess)
+                return false;
+        }
+        if (hipEventRecord(ev[kTuneReps], s) != hipSuccess || hipEventSynchronize(ev[kTuneReps]) != hipSuccess)
+            return false;
+        float v[kTuneReps];
+        for (int r = 0; r < kTuneReps; ++r)
+            if (hipEventElapsedTime(&v[r], ev[r], ev[r + 1]) != hipSuccess) return false;
+        std::sort(v, v + kTuneReps);
+        *ms = v[kTuneReps / 2];
+        return true;
+    };
+    TuneEntry best;
+    best.ms = -1.f;
+    auto consider = [&](const TuneEntry& cand) -> bool {
+        appd_batch_plan p = *plan;
+        apply_entry(cand, &p);
+        float ms = 0.f;
+        if (!measure(&p, cand.split, &ms)) return false;
+        if (best.ms < 0.f || ms < best.ms) {
+            best = cand;
+            best.ms = ms;
+        }
+        return true;
+    };
+    // 1. the launch forms with 16 rows per fill item everywhere and Boruvka
+    //    trees: classes in order, on 3 or 4 streams (with and without the cut
+    //    of the largest class), and the persistent launch
+    TuneEntry base = entry_of(plan);
+    for (int c = 0; c < appd::kBatchClasses; ++c) {
+        base.rows[c] = 16;
+        base.tree[c] = APPD_BATCH_TREE_BORUVKA;
+    }
+    base.persistent = 0;
+    static const int streams_opt[3] = {1, 3, 4};
+    for (int si = 0; si < 3; ++si)
+        for (int sp = 0; sp < 2; ++sp) {
+            if (sp && streams_opt[si] == 1) continue;  // a cut needs two streams
+            TuneEntry c = base;
+            c.streams = streams_opt[si];
+            c.split = sp ? -1 : 0;
+            if (!consider(c)) return hip_fail();
+        }
+    {
+        appd_batch_plan p = *plan;
+        TuneEntry c = base;
+        c.persistent = 1;
+        c.streams = 1;
+        c.split = 0;
+        apply_entry(c, &p);
+        if (persistent_ok(&p) && !consider(c)) return hip_fail();
+    }
+    // 2. per class, largest first: rows per fill item and (launch sequence
+    //    only) the tree: Boruvka, or Prim with a narrow or a wide workgroup
     static const int narrow[appd::kBatchClasses] = {64, 64, 64, 256, 256, 256};
     static const int wide[appd::kBatchClasses] = {64, 128, 256, 512, 512, 1024};
-    static const int rows_opt[3] = {16, 32, 64};
-    // at most 4 streams: a process gets 4 hardware queues by default, and a
-    // fifth stream shares one with another (a kernel trace of a HIP-graph
-    // replay showed a small class queued behind the largest one)
-    static const int streams_opt[3] = {1, 3, 4};
-    appd_batch_plan best = *plan;
-    float best_t = -1.f;
-    for (int wsel = 0; wsel < 2; ++wsel)
+    static const int rows_opt[3] = {8, 16, 32};
+    for (int c = appd::kBatchClasses - 1; c >= 0; --c) {
+        if (!plan->class_count[c]) continue;
+        const TuneEntry cur = best;
         for (int ri = 0; ri < 3; ++ri)
-            for (int si = 0; si < 3; ++si)
-              for (int sp = 0; sp < 2; ++sp) {
-                if (sp && streams_opt[si] == 1) continue;  // a split needs two streams
-                appd_batch_plan p = *plan;
-                for (int c = 0; c < appd::kBatchClasses; ++c) {
-                    p.class_threads[c] = wsel ? wide[c] : narrow[c];
-                    p.class_rows[c] = rows_opt[ri];
-                }
-                p.streams = streams_opt[si];
-                build_chunks(ns.data(), perm, &p, chunk_start, sp ? -1 : 0);
-                if ((e = hipStreamSynchronize(s)) != hipSuccess ||
-                    (e = hipMemcpy(t.chunk_start, chunk_start.data(), 4 * (size_t)G,
-                                   hipMemcpyHostToDevice)) != hipSuccess)
-                    return hip_fail(e);
-                appd::BatchTree tree{t.order, t.ek, t.pos, t.parent};
-                appd::BatchPlan bp = device_plan(&p, t);
-                float tt = 0.f;
-                for (int rep = 0; rep < 3; ++rep) {  // one warm-up, two timed
-                    if (rep == 1 && (e = hipEventRecord(e0, s)) != hipSuccess) return hip_fail(e);
-                    if ((e = appd::run_batched(W, t.offsets, t.ns, bp, tree, t.blk, APPD_MINIMAX, M,
-                                               idx, s)) != hipSuccess)
-                        return hip_fail(e);
-                }
-                if ((e = hipEventRecord(e1, s)) != hipSuccess ||
-                    (e = hipEventSynchronize(e1)) != hipSuccess ||
-                    (e = hipEventElapsedTime(&tt, e0, e1)) != hipSuccess)
-                    return hip_fail(e);
-                tt *= 0.5f;
-                if (best_t < 0.f || tt < best_t) {
-                    best_t = tt;
-                    best = p;
-                }
+            for (int tr = 0; tr < (cur.persistent ? 1 : 3); ++tr) {
+                TuneEntry x = cur;
+                x.rows[c] = rows_opt[ri];
+                x.tree[c] = tr == 0 ? APPD_BATCH_TREE_BORUVKA : APPD_BATCH_TREE_PRIM;
+                x.threads[c] = tr == 2 ? wide[c] : narrow[c];
+                if (x.rows[c] == cur.rows[c] && x.tree[c] == cur.tree[c] &&
+                    (x.tree[c] == APPD_BATCH_TREE_BORUVKA || x.threads[c] == cur.threads[c]))
+                    continue;
+                if (!consider(x)) return hip_fail();
             }
-    build_chunks(ns.data(), perm, &best, chunk_start, best.split_count);
-    if ((e = hipMemcpy(t.chunk_start, chunk_start.data(), 4 * (size_t)G,
-                       hipMemcpyHostToDevice)) != hipSuccess)
-        return hip_fail(e);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    *plan = best;
-    if (best_ms) *best_ms = best_t;
+    }
+    for (hipEvent_t& x : ev) {
+        (void)hipEventDestroy(x);
+        x = nullptr;
+    }
+    appd_batch_plan p = *plan;
+    apply_entry(best, &p);
+    build_chunks(ns.data(), perm, &p, chunk_start, best.split, &items);
+    if (hipStreamSynchronize(s) != hipSuccess || upload_schedule(t, G, chunk_start, items) != hipSuccess)
+        return hip_fail();
+    if (cache && *cache && !key.empty()) cache_store(cache, key, best);
+    *plan = p;
+    if (best_ms) *best_ms = best.ms;
     return ok();
 }
 
 int appd_batch_set_schedule(appd_batch_plan* plan, void* ws, void* stream) {
     if (!plan_ok(plan, ws) || plan->streams < 1 || plan->streams > appd::kBatchClasses ||
-        plan->split_count < -1)
+        plan->split_count < -1 || (plan->persistent != 0 && plan->persistent != 1) ||
+        (plan->persistent && !persistent_ok(plan)))
         return fail(APPD_EINVAL);
     for (int c = 0; c < appd::kBatchClasses; ++c) {
         if (!plan->class_count[c]) continue;
@@ -430,17 +723,16 @@ int appd_batch_set_schedule(appd_batch_plan* plan, void* ws, void* stream) {
     Tables t = carve(ws, G, plan->total_n);
     hipStream_t s = (hipStream_t)stream;
     std::vector<int32_t> ns(G), perm(G), chunk_start;
+    std::vector<uint2> items;
     if (hipStreamSynchronize(s) != hipSuccess ||
         hipMemcpy(ns.data(), t.ns, 4 * (size_t)G, hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(perm.data(), t.perm, 4 * (size_t)G, hipMemcpyDeviceToHost) != hipSuccess)
         return hip_status(hipErrorUnknown);
     appd_batch_plan p = *plan;
     const int want = p.split_count;
-    build_chunks(ns.data(), perm, &p, chunk_start, want);
+    build_chunks(ns.data(), perm, &p, chunk_start, want, &items);
     if (want > 0 && p.split_count != want) return fail(APPD_EINVAL);  // cut out of range
-    if (hipMemcpy(t.chunk_start, chunk_start.data(), 4 * (size_t)G, hipMemcpyHostToDevice) !=
-        hipSuccess)
-        return hip_status(hipErrorUnknown);
+    if (upload_schedule(t, G, chunk_start, items) != hipSuccess) return hip_status(hipErrorUnknown);
     *plan = p;
     return ok();
 }

@@ -31,22 +31,13 @@
 //
 // Outputs per graph (at its noff offset): order, ek (attachment keys in Prim
 // order), pos and parent -- what the sequential kernel writes.
-#include "appd.h"
-#include "appd_device.h"
-#include "appd_internal.h"
-#include "appd_prim.h"
-#include "appd_topk.h"
+#include "appd_btree.h"
 
 namespace appd {
 
 constexpr int kBtPassThreads = 256;  // 4 waves, one row each
-constexpr int kBtRefreshes = 8;      // refreshes of a stuck graph's lists before Prim
-constexpr int kBtK = 16;             // candidate list length
-constexpr uint16_t kNil16 = 0xffff;
 
-// One wave per row of the class (rows of its graphs in perm order; rgraph
-// gives each row's graph position).  The row's candidate list comes from
-// row_topk_rank_vals, or from row_topk where its candidates overflow.
+// One wave per row of the class.
 template <bool WIDEST, int E>
 __global__ __launch_bounds__(kBtPassThreads) void btree_pass_kernel(
     const float* __restrict__ W, const int64_t* __restrict__ offsets,
@@ -54,483 +45,25 @@ __global__ __launch_bounds__(kBtPassThreads) void btree_pass_kernel(
     const int64_t* __restrict__ noff, const int32_t* __restrict__ rstart,
     const int32_t* __restrict__ rgraph, int first, int count, uint64_t* __restrict__ lists) {
     __shared__ uint64_t s_buf[kBtPassThreads / kWave][2 * kWave];
-    const int lane = threadIdx.x & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
     const int r = rstart[first] + (int)blockIdx.x * (kBtPassThreads / kWave) + wid;
     const int rend = rstart[first + count - 1] + ns[perm[first + count - 1]];
     if (r >= rend) return;  // whole wave (r is wave-uniform); no barrier in this kernel
-    const int i = rgraph[r];
-    const int g = perm[i];
-    const int n = ns[g];
-    const int u = r - rstart[i];
-    const float* row = W + offsets[g] + (size_t)u * n;
-    float x[E];
-    rank_row_load<E>(row, n, x);
-    uint64_t mine;
-    if (!row_topk_rank_vals<WIDEST, E, kBtK>(x, n, u, s_buf[wid], &mine))
-        mine = row_topk<WIDEST, false, false, E, kBtK>(
-            row, n, u, [](int) { return 0; }, [](int) { return make_int4(0, 0, 0, 0); });
-    if (lane < kBtK) lists[(size_t)(noff[g] + u) * kBtK + lane] = mine;
+    bt_pass_row<WIDEST, E>(W, offsets, ns, perm, noff, rstart, rgraph, r, lists, s_buf[wid]);
 }
 
-// Block-wide exclusive scan over NT threads; s: NT / 64 ints.
-template <int NT>
-__device__ __forceinline__ int bt_excl_scan(int x, int* s, int* total) {
-    constexpr int NW = NT / kWave;
-    const int t = threadIdx.x, lane = t & (kWave - 1), wid = t / kWave;
-    int incl = x;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int y = __shfl_up(incl, d);
-        if (lane >= d) incl += y;
-    }
-    if (lane == kWave - 1) s[wid] = incl;
-    __syncthreads();
-    int before = 0, all = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        const int v = s[w];
-        before += w < wid ? v : 0;
-        all += v;
-    }
-    __syncthreads();
-    *total = all;
-    return before + incl - x;
-}
-
-// LDS of one graph, nmax = the class's largest n (bytes: 39 * nmax, see
-// btree_lds_bytes).  The rounds' per-component tables and the order phase's
-// per-vertex arrays share the same regions.
-struct BtLds {
-    uint64_t* a8;   // rounds: best[c]   order: keyup[v]
-    uint64_t* b8;   // rounds: lb[c]     order: packed (size << 12 | arrivals)[v], then S[v]
-    int32_t* c4;    // rounds: hook[c]   order: link[v]
-    int32_t* d4;    // rounds: hx[c]     order: gcount[v]
-    int32_t* e4;    // rounds: hy[c]     order: gstart[v]
-    int32_t* f4;    //                   order: group fill counters
-    uint16_t* comp; // component of each vertex (dense ids)
-    uint16_t* par;  // rooted forest (kNil16: root)
-    uint16_t* mem;  // order: group members
-    uint8_t* lptr;  // list pointer of each vertex
-};
-
-size_t btree_lds_bytes(int nmax) { return (size_t)39 * nmax + 64; }
-
-__device__ __forceinline__ BtLds bt_carve(void* base, int nmax) {
-    char* p = (char*)base;
-    BtLds L;
-    L.a8 = (uint64_t*)p;
-    p += 8 * nmax;
-    L.b8 = (uint64_t*)p;
-    p += 8 * nmax;
-    L.c4 = (int32_t*)p;
-    p += 4 * nmax;
-    L.d4 = (int32_t*)p;
-    p += 4 * nmax;
-    L.e4 = (int32_t*)p;
-    p += 4 * nmax;
-    L.f4 = (int32_t*)p;
-    p += 4 * nmax;
-    L.comp = (uint16_t*)p;
-    p += 2 * nmax;
-    L.par = (uint16_t*)p;
-    p += 2 * nmax;
-    L.mem = (uint16_t*)p;
-    p += 2 * nmax;
-    L.lptr = (uint8_t*)p;
-    return L;
-}
-
-// Ascending bitonic sort of key[0 .. N) (N a power of two) with a 16-bit
-// payload, by the NT threads of the workgroup.
-template <int NT, class K>
-__device__ __forceinline__ void bt_bitonic(K* key, uint16_t* pay, int N) {
-    for (int size = 2; size <= N; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            __syncthreads();
-            for (int i = threadIdx.x; i < N / 2; i += NT) {
-                const int a = 2 * i - (i & (stride - 1));
-                const int b = a + stride;
-                const bool up = (a & size) == 0;
-                const K ka = key[a], kb = key[b];
-                if ((ka > kb) == up) {
-                    key[a] = kb;
-                    key[b] = ka;
-                    const uint16_t pa = pay[a];
-                    pay[a] = pay[b];
-                    pay[b] = pa;
-                }
-            }
-        }
-    }
-    __syncthreads();
-}
-
+// One workgroup per graph of the class.
 template <int NT, int CH, bool WIDEST>
 __global__ __launch_bounds__(NT) void btree_finish_kernel(
     const float* __restrict__ Wall, const int64_t* __restrict__ offsets,
     const int32_t* __restrict__ ns, const int32_t* __restrict__ perm,
     const int64_t* __restrict__ noff, int first, int nmax, uint64_t* __restrict__ lists_all,
     BatchTree tree, int32_t* __restrict__ tstats, BatchBlk blk) {
-    constexpr int NW = NT / kWave;
     extern __shared__ uint64_t s_dyn[];
-    __shared__ int s_segv[NT], s_segh[NT];
-    __shared__ uint64_t red_key[2 * NW];
-    __shared__ int32_t red_v[2 * NW];
-    __shared__ int s_wsum[NW];
-    __shared__ int s_flag[4];
-    const int t = threadIdx.x, lane = t & (kWave - 1), wid = t / kWave;
-    const int g = perm[first + blockIdx.x];
-    const int n = ns[g];
-    const int64_t o = noff[g];
-    const float* W = Wall + offsets[g];
-    uint64_t* lists = lists_all + (size_t)o * kBtK;
-    PrimOut out{tree.order + o, tree.ek + o, tree.pos + o, tree.parent + o};
-    if (n == 1) {
-        if (t == 0) {
-            tstats[g] = 1 << 8;
-            blk.slot[o] = 0;
-            blk.dM[o] = 0.0f;
-            blk.dI[o] = -1;
-            out.order[0] = 0;
-            out.ek[0] = 0;
-            out.pos[0] = 0;
-            out.parent[0] = -1;
-        }
-        return;
-    }
-    BtLds L = bt_carve(s_dyn, nmax);
-    const uint32_t un = (uint32_t)n;
-    for (int v = t; v < n; v += NT) {
-        L.comp[v] = (uint16_t)v;
-        L.par[v] = kNil16;
-        L.lptr[v] = 0;
-    }
-    int C = n;
-    int nrounds = 0, nrefresh = 0;
-    __syncthreads();
-    for (int guard = 0; guard < 96 && C > 1; ++guard) {
-        {
-            ++nrounds;
-            // 1. every vertex's first list entry outside its component, or its
-            //    bound.  The entries from the list pointer on are read eight at
-            //    a time (independent loads), then checked in order.
-            for (int d = t; d < C; d += NT) L.a8[d] = L.b8[d] = kTopkNone;
-            if (t == 0) s_flag[0] = 0;
-            __syncthreads();
-            for (int v = t; v < n; v += NT) {
-                const int cv = L.comp[v];
-                const uint64_t* lv = lists + (size_t)v * kBtK;
-                int p = L.lptr[v];
-                int state = 0;  // 0 searching, 1 external entry at p, 2 list ended, 3 used up
-                uint64_t e = kTopkNone;
-                while (state == 0) {
-                    if (p >= kBtK) {
-                        state = 3;
-                        break;
-                    }
-                    uint64_t w[8];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) w[j] = lv[min(p + j, kBtK - 1)];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        if (state != 0) continue;
-                        if (p + j >= kBtK) {
-                            state = 3;
-                            continue;
-                        }
-                        const uint64_t x = w[j];
-                        if ((uint32_t)x >= un) {  // end of the list (or not a vertex)
-                            state = 2;
-                            p += j;
-                        } else if ((int)L.comp[(uint32_t)x] != cv) {
-                            state = 1;
-                            e = x;
-                            p += j;
-                        }
-                    }
-                    if (state == 0) p += 8;
-                    if (state == 3) p = kBtK;
-                }
-                L.lptr[v] = (uint8_t)p;
-                if (state == 1) {
-                    const uint64_t k = (e & 0xffffffff00000000ull) | flat_idx((uint32_t)v, (uint32_t)e, un);
-                    atomicMin((unsigned long long*)&L.a8[cv], (unsigned long long)k);
-                } else if (state == 3) {
-                    // a full list, every entry inside the component: every
-                    // outgoing edge of v is larger than its last entry
-                    const uint64_t last = lv[kBtK - 1];  // a vertex (checked above)
-                    const uint64_t k =
-                        (last & 0xffffffff00000000ull) | flat_idx((uint32_t)v, (uint32_t)last, un);
-                    atomicMin((unsigned long long*)&L.b8[cv], (unsigned long long)k);
-                }
-                // state 2: the list held every eligible entry of the row: no bound
-            }
-            __syncthreads();
-            // 2. decide: hook when the best candidate beats every bound
-            for (int d = t; d < C; d += NT) {
-                const uint64_t b = L.a8[d];
-                L.c4[d] = d;
-                if (b != kTopkNone && b < L.b8[d]) {
-                    const uint32_t f = (uint32_t)b;
-                    const int x0 = (int)(f / un), y0 = (int)(f % un);
-                    const bool xin = L.comp[x0] == d;
-                    const int x = xin ? x0 : y0, y = xin ? y0 : x0;
-                    L.d4[d] = x;
-                    L.e4[d] = y;
-                    L.c4[d] = L.comp[y];
-                    atomicAdd(&s_flag[0], 1);
-                }
-            }
-            __syncthreads();
-            const int decided = s_flag[0];
-            __syncthreads();
-            if (decided == 0) {
-                // No component can decide: the smallest component's vertices get
-                // fresh lists of their entries outside it (exact candidates), so
-                // that it decides in the next round.  After kBtRefreshes such
-                // refreshes Prim's algorithm finishes the graph instead.
-                if (nrefresh == kBtRefreshes) break;
-                ++nrefresh;
-                for (int d = t; d < C; d += NT) L.d4[d] = 0;
-                if (t == 0) s_flag[2] = 0x7fffffff;
-                __syncthreads();
-                for (int v = t; v < n; v += NT) atomicAdd(&L.d4[L.comp[v]], 1);
-                __syncthreads();
-                for (int d = t; d < C; d += NT) atomicMin(&s_flag[2], (L.d4[d] << 16) | d);
-                __syncthreads();
-                const int sc = s_flag[2] & 0xffff;
-                for (int u = wid; u < n; u += NW) {  // u wave-uniform
-                    if ((int)L.comp[u] != sc) continue;
-                    constexpr int kRefE = NT * CH / 64 < 4 ? 4 : (NT * CH / 64 > 32 ? 32 : NT * CH / 64);
-                    const uint64_t mine = row_topk<WIDEST, true, false, kRefE, kBtK>(
-                        W + (size_t)u * n, n, u, [&](int c) { return (int)L.comp[c]; },
-                        [](int) { return make_int4(0, 0, 0, 0); });
-                    if (lane < kBtK) lists[(size_t)u * kBtK + lane] = mine;
-                    if (lane == 0) L.lptr[u] = 0;
-                }
-                __syncthreads();
-                continue;
-            }
-            // 3. a mutual pair chose the same edge: the smaller id stays the
-            //    root; every other hooking component re-roots at its endpoint
-            for (int d = t; d < C; d += NT) {
-                const int h = L.c4[d];
-                if (h == d) continue;
-                if (d < h && L.c4[h] == d && L.a8[h] == L.a8[d]) {
-                    L.c4[d] = d;
-                    continue;
-                }
-                int cur = L.d4[d], prev = L.e4[d];
-                while (cur != kNil16) {
-                    const int nxt = L.par[cur];
-                    L.par[cur] = (uint16_t)prev;
-                    prev = cur;
-                    cur = nxt;
-                }
-            }
-            __syncthreads();
-            // 4. pointer jumping: every component -> the root it now belongs to
-            for (int it = 0; it < 32; ++it) {
-                if (t == 0) s_flag[1] = 0;
-                __syncthreads();
-                for (int d = t; d < C; d += NT) {
-                    const int h = L.c4[d];
-                    const int hh = L.c4[h];
-                    if (hh != h) {
-                        L.c4[d] = hh;
-                        s_flag[1] = 1;
-                    }
-                }
-                __syncthreads();
-                const int again = s_flag[1];
-                __syncthreads();
-                if (!again) break;
-            }
-            // 5. dense numbers of the roots (kept in d4 of each root)
-            const int per = (C + NT - 1) / NT;
-            const int d0 = min(C, t * per), d1 = min(C, d0 + per);
-            int cnt = 0;
-            for (int d = d0; d < d1; ++d) cnt += L.c4[d] == d ? 1 : 0;
-            int total;
-            int id = bt_excl_scan<NT>(cnt, s_wsum, &total);
-            for (int d = d0; d < d1; ++d)
-                if (L.c4[d] == d) L.d4[d] = id++;
-            __syncthreads();
-            // 6. relabel every vertex
-            for (int v = t; v < n; v += NT) L.comp[v] = (uint16_t)L.d4[L.c4[L.comp[v]]];
-            C = total;
-            __syncthreads();
-        }
-    }
-    const bool done = C == 1;
-    if (t == 0) tstats[g] = min(nrounds, 255) | ((1 + nrefresh) << 8) | ((done ? 0 : 1) << 16);
-    if (!done) {
-        // the lists could not finish the tree: Prim's algorithm (same outputs)
-        __syncthreads();
-        prim_run<NT, CH, WIDEST>(W, n, out, red_key, red_v);
-        __syncthreads();
-        // the fill's rank tables from Prim's attachment keys
-        uint64_t* skey = (uint64_t*)L.d4;
-        for (int i = t; i < nmax; i += NT) {
-            skey[i] = (i >= 1 && i < n) ? out.ek[i] : ~0ull;  // position i's key
-            L.comp[i] = (uint16_t)i;
-        }
-        bt_bitonic<NT>(skey, L.comp, nmax);
-        for (int r = t; r < n; r += NT) {
-            if (r == 0) {
-                blk.slot[o] = 0;
-                blk.dM[o] = 0.0f;
-                blk.dI[o] = -1;
-                continue;
-            }
-            const int k = L.comp[r - 1];  // position of the key of rank r - 1
-            const uint64_t key = skey[r - 1];
-            blk.slot[o + k] = (uint16_t)r;
-            blk.dM[o + r] = key_weight<WIDEST>(key);
-            blk.dI[o + r] = (int32_t)(uint32_t)key;
-        }
-        return;
-    }
-    // re-root the tree at vertex 0
-    if (t == 0) {
-        int cur = 0, prev = kNil16;
-        while (cur != kNil16) {
-            const int nxt = L.par[cur];
-            L.par[cur] = (uint16_t)prev;
-            prev = cur;
-            cur = nxt;
-        }
-    }
-    __syncthreads();
-    // ---- Prim's order from the tree
-    uint64_t* keyup = L.a8;
-    uint32_t* pk = (uint32_t*)L.b8;   // (size << 12) | arrivals
-    uint32_t* S = pk + nmax;          // sizes of the smaller siblings
-    int32_t* link = L.c4;
-    int32_t* gcount = L.d4;
-    for (int v = t; v < n; v += NT) {
-        const int p = v ? (int)L.par[v] : -1;
-        uint64_t k = 0;
-        if (p >= 0) k = make_key((WIDEST ? -1.0f : 1.0f) * W[(size_t)v * n + p], flat_idx(v, p, un));
-        keyup[v] = k;
-        link[v] = p;
-        gcount[v] = 0;
-        pk[v] = 1u << 12;
-    }
-    __syncthreads();
-    // link(v): jump over ancestors whose edge is smaller than e(v).  Any value
-    // a link entry holds at any time is an ancestor reached over smaller edges
-    // only, so a thread may follow entries other threads still update.
-    volatile int32_t* vlink = link;
-    for (int v = t; v < n; v += NT) {
-        if (v == 0) continue;
-        const uint64_t kv = keyup[v];
-        int c = vlink[v];
-        while (c > 0 && keyup[c] < kv) {
-            c = vlink[c];
-            vlink[v] = c;
-        }
-    }
-    __syncthreads();
-    for (int v = t; v < n; v += NT)
-        if (v) atomicAdd(&gcount[link[v]], 1);
-    __syncthreads();
-    // link-subtree sizes bottom-up: a walk starts at every leaf; one packed
-    // atomic adds a child's size and its arrival, and the child that arrives
-    // last reads the parent's final size from the value it returns
-    for (int v = t; v < n; v += NT) {
-        if (v == 0 || gcount[v] != 0) continue;
-        int x = v;
-        uint32_t sx = 1;
-        for (int guard = 0; guard < n; ++guard) {
-            const int p = link[x];
-            if (p <= 0) break;
-            const uint32_t old = atomicAdd(&pk[p], (sx << 12) | 1u);
-            if ((int)(old & 0xfffu) + 1 != gcount[p]) break;
-            sx += old >> 12;
-            x = p;
-        }
-    }
-    __syncthreads();
-    // S(v), the total link-subtree size of v's siblings with smaller keys:
-    // (a) the vertices 1..n-1 sorted by edge key give each its key rank; (b)
-    // sorted by (link parent, key rank) they come grouped by sibling set in
-    // key order; (c) an exclusive scan of the sizes restarted at every group
-    // gives S.  Keys are distinct, ranks are < 2048 and parents < 2048.
-    uint64_t* skey = (uint64_t*)L.d4;  // d4 and e4: 8 bytes per entry
-    uint32_t* skey2 = (uint32_t*)L.d4;
-    int32_t* rankv = L.f4;
-    for (int i = t; i < nmax; i += NT) {
-        skey[i] = (i >= 1 && i < n) ? keyup[i] : ~0ull;
-        L.comp[i] = (uint16_t)i;
-    }
-    bt_bitonic<NT>(skey, L.comp, nmax);
-    for (int i = t; i < n - 1; i += NT) rankv[L.comp[i]] = i;
-    __syncthreads();
-    for (int i = t; i < nmax; i += NT) {
-        skey2[i] = (i >= 1 && i < n) ? ((uint32_t)link[i] << 11) | (uint32_t)rankv[i] : ~0u;
-        L.comp[i] = (uint16_t)i;
-    }
-    bt_bitonic<NT>(skey2, L.comp, nmax);
-    {
-        // segmented exclusive scan over positions 0 .. n-2: thread t takes a
-        // run of consecutive positions; (sum since the last group start, seen a
-        // start) per run, combined across threads
-        const int m = n - 1;
-        const int per = (m + NT - 1) / NT;
-        const int i0 = min(m, t * per), i1 = min(m, i0 + per);
-        int tot = 0, head = 0;
-        for (int i = i0; i < i1; ++i) {
-            if (i == 0 || (skey2[i] >> 11) != (skey2[i - 1] >> 11)) {
-                tot = 0;
-                head = 1;
-            }
-            tot += (int)(pk[L.comp[i]] >> 12);
-        }
-        s_segv[t] = tot;
-        s_segh[t] = head;
-        __syncthreads();
-        // inclusive segmented scan of the runs: (v, h) + (v', h') = (h' ? v' : v + v', h | h')
-        for (int d = 1; d < NT; d <<= 1) {
-            int pv = 0, ph = 0;
-            if (t >= d) {
-                pv = s_segv[t - d];
-                ph = s_segh[t - d];
-            }
-            __syncthreads();
-            if (t >= d && !s_segh[t]) {
-                s_segv[t] += pv;
-                s_segh[t] |= ph;
-            }
-            __syncthreads();
-        }
-        int run = t == 0 ? 0 : s_segv[t - 1];
-        for (int i = i0; i < i1; ++i) {
-            if (i == 0 || (skey2[i] >> 11) != (skey2[i - 1] >> 11)) run = 0;
-            const int v = L.comp[i];
-            S[v] = (uint32_t)run;
-            run += (int)(pk[v] >> 12);
-        }
-    }
-    __syncthreads();
-    // pos(v) = sum over v and its link ancestors below the root of 1 + S
-    for (int v = t; v < n; v += NT) {
-        int p = 0;
-        for (int x = v; x > 0; x = link[x]) p += 1 + (int)S[x];
-        p = min(p, n - 1);  // a position is always < n; never write outside the graph
-        out.pos[v] = p;
-        out.order[p] = v;
-        out.ek[p] = keyup[v];
-        out.parent[v] = v ? (int)L.par[v] : -1;
-        // the fill's tables: rank code of each position (1 + the rank of its
-        // key among the n - 1 keys; 0 at position 0), and each code's weight
-        // and flat index (code 0: the diagonal)
-        const int r = v ? rankv[v] + 1 : 0;
-        blk.slot[o + p] = (uint16_t)r;
-        blk.dM[o + r] = v ? key_weight<WIDEST>(keyup[v]) : 0.0f;
-        blk.dI[o + r] = v ? (int32_t)(uint32_t)keyup[v] : -1;
-    }
+    __shared__ uint64_t s_aux[(bt_aux_bytes<NT>() + 7) / 8];
+    const BtAux aux = bt_aux_carve<NT>((char*)s_aux);
+    bt_finish_graph<NT, CH, WIDEST>(Wall, offsets, ns, perm, noff, first + (int)blockIdx.x, nmax,
+                                    lists_all, tree, tstats, blk, s_dyn, aux);
 }
 
 template <bool WIDEST>

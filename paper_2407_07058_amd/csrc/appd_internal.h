@@ -111,6 +111,13 @@ struct BatchPlan {
     int streams;
     int split_count;   // largest class: graphs launched first on their own (0: no split)
     int split_chunks;  // their fill work items
+    // the persistent form (see appd_persist.hip)
+    int persistent;
+    int persist_items;
+    int num_graphs;
+    int total_n;
+    const uint2* items;  // [persist_items] work queue (device)
+    int* ctr;            // [2 + 2 G] queue head, rows done and tree done per graph, abort (device)
 };
 
 int batch_class_of(int n);
@@ -122,6 +129,21 @@ bool batch_threads_ok(int c, int threads);
 hipError_t run_batched(const float* W, const int64_t* offsets, const int32_t* ns,
                        const BatchPlan& plan, const BatchTree& tree, const BatchBlk& blk,
                        int mode, float* M, int32_t* idx, hipStream_t s);
+hipError_t run_persistent(const float* W, const int64_t* offsets, const int32_t* ns,
+                          const BatchPlan& plan, const BatchTree& tree, const BatchBlk& blk,
+                          int mode, float* M, int32_t* idx, hipStream_t s);
+// Persistent form: rows per pass item (one per wave of its workgroup) and the
+// class limit.
+constexpr int kPersistThreads = 512;
+constexpr int kPersistMaxN = 1024;
+// Work item words: x = type << 30 | first row (pass) or graph position (tree,
+// fill); y (fill) = first row | row count << 16.
+constexpr uint32_t kItemPass = 0u, kItemTree = 1u, kItemFill = 2u;
+
+// Per-GPU status record read and cleared by appd_sync: validation flags of
+// checked forwards, and kStatusWaitTimeout.
+uint32_t* device_status_word();
+constexpr uint32_t kStatusWaitTimeout = 0x100u;
 
 // ---- points / gradients
 hipError_t run_pairwise(const float* X, const int64_t* xoff, const int64_t* offsets,

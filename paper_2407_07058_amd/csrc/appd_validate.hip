@@ -98,6 +98,8 @@ uint32_t* pending_for_current_device() {
 
 }  // namespace
 
+uint32_t* device_status_word() { return pending_for_current_device(); }
+
 hipError_t enqueue_input_check(const float* W, int n, hipStream_t s) {
     uint32_t* pending = pending_for_current_device();
     if (!pending) return hipErrorUnknown;
@@ -133,7 +135,9 @@ extern "C" int appd_sync(void* stream) {
             return APPD_EHIP;
         }
     }
-    const int rc = (flags & (APPD_VALID_NAN | APPD_VALID_ASYM)) ? APPD_EDATA : APPD_OK;
+    const int rc = (flags & appd::kStatusWaitTimeout) ? APPD_EHIP
+                   : (flags & (APPD_VALID_NAN | APPD_VALID_ASYM)) ? APPD_EDATA
+                                                                  : APPD_OK;
     appd::set_last_error(rc);
     return rc;
 }

@@ -245,6 +245,109 @@ def test_batched_autotune_bit_exact():
         assert np.array_equal(Ms[g].view(np.uint32), Mo.view(np.uint32)) and np.array_equal(Is[g], io), g
 
 
+def small_mixed_graphs(seed):
+    """mixed_graphs without the sizes above 1024 (the persistent form's limit)."""
+    return [W for W in mixed_graphs(seed) if W.shape[0] <= 1024]
+
+
+def test_batched_persistent_form():
+    """The whole forward as one persistent launch over the work queue (pass,
+    tree and fill items with in-queue dependencies): every graph equals the
+    oracle, at several rows per fill item, in both modes; a batch with a graph
+    above 1024 vertices cannot take this form."""
+    say("case batched persistent form")
+    Ws = small_mixed_graphs(9)
+    flat, offsets, ns = workloads.pack(Ws)
+    Wd = torch.from_numpy(flat).to(DEV)
+    for rows in (16, 5, 64):
+        b = appd.Batch(ns, DEV)
+        b.set_schedule(rows=rows, persistent=True)
+        assert b.schedule()["persistent"] == 1 and b.plan.persist_items > 0
+        for mode, ref in ((appd.MINIMAX, oracle.appd), (appd.WIDEST, oracle.appd_widest)):
+            M, idx = b.forward(Wd, mode=mode)
+            appd.sync(DEV)  # also reports a wait of the launch that gave up
+            Ms = unpack(M.cpu().numpy(), ns, offsets)
+            Is = unpack(idx.cpu().numpy(), ns, offsets)
+            for g, W in enumerate(Ws):
+                Mo, io = ref(W)
+                assert np.array_equal(Ms[g].view(np.uint32), Mo.view(np.uint32)), (rows, mode, g)
+                assert np.array_equal(Is[g], io), (rows, mode, g)
+    big = mixed_graphs(9)
+    _, _, ns_big = workloads.pack(big)
+    b = appd.Batch(ns_big, DEV)
+    with pytest.raises(appd.APPDError):
+        b.set_schedule(persistent=True)
+
+
+def test_batched_persistent_ragged_and_capture():
+    """The persistent form on the ragged 4096-graph batch equals the launch
+    sequence bit for bit, and inside a HIP graph every replay equals it too
+    (the queue counters are cleared by a kernel, not a memset)."""
+    say("case persistent ragged batch + capture")
+    with pool() as ex:
+        Ws = list(ex.map(workloads.euclid_w, workloads.ragged_points()))
+    flat, offsets, ns = workloads.pack(Ws)
+    del Ws
+    Wd = torch.from_numpy(flat).to(DEV)
+    M0, I0 = appd.Batch(ns, DEV).forward(Wd)
+    b = appd.Batch(ns, DEV)
+    b.set_schedule(persistent=True)
+    M, I = b.forward(Wd)
+    appd.sync(DEV)
+    assert torch.equal(M, M0) and torch.equal(I, I0)
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.forward(Wd, out=(M, I))
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        b.forward(Wd, out=(M, I))
+    for rep in range(3):
+        M.fill_(-7.0)
+        I.fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        appd.sync(DEV)
+        assert torch.equal(M, M0) and torch.equal(I, I0), "replay %d differs" % rep
+
+
+def test_batched_autotune_plan_cache(tmp_path, monkeypatch):
+    """APPD_TUNE_CACHE: the first autotune times the candidates and stores the
+    winner under this GPU and class histogram; the file is one JSON object; a
+    second Batch of the same histogram takes the stored schedule without
+    timing (same milliseconds back, same schedule) and still matches the
+    oracle."""
+    import json
+    say("case autotune plan cache")
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("APPD_TUNE_CACHE", str(path))
+    Ws = small_mixed_graphs(10)
+    flat, offsets, ns = workloads.pack(Ws)
+    Wd = torch.from_numpy(flat).to(DEV)
+    b1 = appd.Batch(ns, DEV)
+    ms1 = b1.autotune(Wd)
+    data = json.loads(path.read_text())
+    assert len(data) == 1
+    (key, entry), = data.items()
+    assert "classes" in key and abs(entry["ms"] - ms1) < 1e-3
+    assert entry["streams"] == b1.plan.streams and entry["persistent"] == b1.plan.persistent
+    b2 = appd.Batch(ns, DEV)
+    ms2 = b2.autotune(Wd)
+    assert abs(ms2 - entry["ms"]) < 1e-3
+    s1, s2 = b1.schedule(), b2.schedule()
+    for k in ("class_rows", "class_tree", "streams", "persistent"):
+        assert s1[k] == s2[k], k
+    M, idx = b2.forward(Wd)
+    torch.cuda.synchronize()
+    Ms = unpack(M.cpu().numpy(), ns, offsets)
+    Is = unpack(idx.cpu().numpy(), ns, offsets)
+    for g, W in enumerate(Ws):
+        Mo, io = oracle.appd(W)
+        assert np.array_equal(Ms[g].view(np.uint32), Mo.view(np.uint32)) and np.array_equal(Is[g], io), g
+
+
 def test_batched_streams_graph_capture_replays():
     """Classes on concurrent library streams (fork/join events) inside a HIP
     graph: every replay equals the eager result."""

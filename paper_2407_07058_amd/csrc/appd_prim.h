@@ -11,6 +11,11 @@
 // "smaller weight, then smaller parent id" -- the tie rule needs no flat index
 // during the update.  A visited vertex holds NaN, which no comparison selects.
 //
+// With more than 24 vertices per thread the parents of the best edges live in
+// LDS as 16-bit ids (kp_lds, NT * CH entries, one per owned vertex slot; n <=
+// 46340 fits), so that the weights and the streamed row stay in registers
+// without spilling; they are read only on a tie, a rescan and an attachment.
+//
 // Each step: the thread's best key (packed 64-bit, see appd_device.h) is
 // reduced across the wave with DPP moves and across waves through LDS (one
 // barrier per step, double-buffered slots); the winner p is recorded; row p is
@@ -29,11 +34,19 @@ struct PrimOut {
     int32_t* parent;  // parent[v] = tree vertex v attached to; parent[0] = -1
 };
 
+// Whether prim_run keeps the parents in LDS (the caller then passes kp_lds).
+template <int CH>
+constexpr bool prim_parents_in_lds() {
+    return CH > 24;
+}
+
 template <int NT, int CH, bool WIDEST>
 __device__ __forceinline__ void prim_run(const float* __restrict__ W, int n, PrimOut out,
-                                         uint64_t* red_key, int32_t* red_v) {
+                                         uint64_t* red_key, int32_t* red_v,
+                                         uint16_t* kp_lds = nullptr) {
     static_assert((NT & (NT - 1)) == 0 && NT >= kWave, "NT must be a power of two >= 64");
     constexpr int NW = NT / kWave;
+    constexpr bool KPL = prim_parents_in_lds<CH>();
     const int t = threadIdx.x;
     const int lane = t & (kWave - 1);
     const int wid = t / kWave;
@@ -41,11 +54,16 @@ __device__ __forceinline__ void prim_run(const float* __restrict__ W, int n, Pri
     const float qnan = __uint_as_float(0x7fc00000u);
 
     float kw[CH];
-    int32_t kp[CH];
+    int32_t kp[KPL ? 1 : CH];
+    auto getkp = [&](int j) -> int32_t { return KPL ? (int32_t)kp_lds[t + NT * j] : kp[j]; };
+    auto setkp = [&](int j, int32_t p) {
+        if (KPL) kp_lds[t + NT * j] = (uint16_t)p;
+        else kp[j] = p;
+    };
 #pragma unroll
     for (int j = 0; j < CH; ++j) {
         const int v = t + NT * j;
-        kp[j] = 0;
+        setkp(j, 0);
         if (v < n && v != 0) {
             const float w = W[v];
             kw[j] = WIDEST ? -w : w;
@@ -59,11 +77,15 @@ __device__ __forceinline__ void prim_run(const float* __restrict__ W, int n, Pri
     auto rescan = [&]() {
         bkey = ~0ull;
         bv = -1;
+        // the vertex ids are recomputed here, not kept live across the steps
+        // (CH of them would take as many registers)
+        int tt = t;
+        asm volatile("" : "+v"(tt));
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
             if (kw[j] == kw[j]) {
-                const uint32_t v = (uint32_t)(t + NT * j);
-                const uint64_t k = make_key(kw[j], flat_idx((uint32_t)kp[j], v, un));
+                const uint32_t v = (uint32_t)(tt + NT * j);
+                const uint64_t k = make_key(kw[j], flat_idx((uint32_t)getkp(j), v, un));
                 if (k < bkey) {
                     bkey = k;
                     bv = (int32_t)v;
@@ -106,14 +128,20 @@ __device__ __forceinline__ void prim_run(const float* __restrict__ W, int n, Pri
         // vertex; keep every address in bounds and carry on deterministically.
         if (p < 0 || p >= n) p = 0;
 
-        // ---- stream row p
-        const float* row = W + (size_t)p * (size_t)n;
-        float r[CH];
+        // ---- stream row p: buffer loads over the row's range (columns past n
+        // read 0 and touch no memory), one offset register for all of them.
+        // Above 32 vertices per thread the row goes through a ring of RB
+        // registers: the load of slot j + RB is issued as slot j is used.
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(W + (size_t)p * (size_t)n), (short)0, n * 4, 0x00020000);
+        constexpr int RB = CH > 32 ? (CH + 1) / 2 : CH;
+        auto load = [&](int j) {
+            return __builtin_bit_cast(float,
+                                      __builtin_amdgcn_raw_buffer_load_b32(rs, 4 * t, 4 * NT * j, 0));
+        };
+        float r[RB];
 #pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            const int v = t + NT * j;
-            r[j] = v < n ? row[v] : 0.0f;
-        }
+        for (int j = 0; j < RB; ++j) r[j] = load(j);
 
         if (t == 0) {
             out.order[k] = p;
@@ -125,7 +153,7 @@ __device__ __forceinline__ void prim_run(const float* __restrict__ W, int n, Pri
 #pragma unroll
             for (int j = 0; j < CH; ++j) {
                 if (t + NT * j == p) {
-                    out.parent[p] = kp[j];
+                    out.parent[p] = getkp(j);
                     kw[j] = qnan;
                 }
             }
@@ -135,18 +163,23 @@ __device__ __forceinline__ void prim_run(const float* __restrict__ W, int n, Pri
         bool have = false;
         float cw = 0.0f;
         int32_t cv = 0;
+        int tu = t;
+        asm volatile("" : "+v"(tu));
 #pragma unroll
         for (int j = 0; j < CH; ++j) {
-            const float w = WIDEST ? -r[j] : r[j];
+            const float x = r[j % RB];
+            if (j + RB < CH) r[j % RB] = load(j + RB);
+            const float w = WIDEST ? -x : x;
             const float cur = kw[j];
-            const bool upd = (w < cur) || (w == cur && p < kp[j]);
+            bool upd = w < cur;
+            if (!upd && w == cur) upd = p < getkp(j);  // a tie: the smaller parent id
             if (upd) {
                 kw[j] = w;
-                kp[j] = p;
+                setkp(j, p);
                 if (!have || w < cw) {  // v grows with j: ties keep the smaller v
                     have = true;
                     cw = w;
-                    cv = t + NT * j;
+                    cv = tu + NT * j;
                 }
             }
         }

@@ -17,7 +17,8 @@ __global__ __launch_bounds__(kPrimThreads) void prim_single_kernel(const float* 
                                                                    int n, PrimOut out) {
     __shared__ uint64_t red_key[2 * (kPrimThreads / kWave)];
     __shared__ int32_t red_v[2 * (kPrimThreads / kWave)];
-    prim_run<kPrimThreads, CH, WIDEST>(W, n, out, red_key, red_v);
+    extern __shared__ uint16_t s_parents[];  // prim_parents_in_lds<CH>(): kPrimThreads * CH
+    prim_run<kPrimThreads, CH, WIDEST>(W, n, out, red_key, red_v, s_parents);
 }
 
 template <int CB, bool WIDEST>
@@ -71,8 +72,15 @@ static hipError_t launch_prim(const float* W, int n, PrimOut out, hipStream_t s)
     const int ch = (n + kPrimThreads - 1) / kPrimThreads;
 #define APPD_PRIM_CASE(C)                                                                    \
     if (ch <= C) {                                                                           \
+        const size_t lds = prim_parents_in_lds<C>() ? (size_t)2 * kPrimThreads * C : 0;     \
+        if (lds > 0) {                                                                       \
+            const hipError_t e = hipFuncSetAttribute(                                        \
+                (const void*)prim_single_kernel<C, WIDEST>,                                  \
+                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                       \
+            if (e != hipSuccess) return e;                                                   \
+        }                                                                                    \
         APPD_LAUNCH("prim_single_kernel", s,                                                 \
-                    prim_single_kernel<C, WIDEST><<<1, kPrimThreads, 0, s>>>(W, n, out));    \
+                    prim_single_kernel<C, WIDEST><<<1, kPrimThreads, lds, s>>>(W, n, out));  \
         return hipGetLastError();                                                            \
     }
     APPD_PRIM_CASE(1)

@@ -1351,10 +1351,11 @@ __global__ __launch_bounds__(1024) void tree_finish_kernel(const float* __restri
                                                           int32_t* ctrl) {
     __shared__ uint64_t red_key[2 * 16];
     __shared__ int32_t red_v[2 * 16];
+    extern __shared__ uint16_t s_parents[];  // prim_parents_in_lds<CH>(): 1024 * CH
     if (blockIdx.x == 0) {
         if (ctrl[C_DONE]) return;
         if (threadIdx.x == 0) ctrl[C_FALLBACK] = 1;
-        prim_run<1024, CH, WIDEST>(W, n, out, red_key, red_v);
+        prim_run<1024, CH, WIDEST>(W, n, out, red_key, red_v, s_parents);
         return;
     }
     if (!ctrl[C_ORDERED]) return;
@@ -1412,8 +1413,15 @@ static hipError_t launch_finish(const float* W, int n, PrimOut out, const TreeWs
     const int blocks = 1 + (n + 1023) / 1024;
 #define APPD_FIN(C)                                                                        \
     if (ch <= C) {                                                                         \
+        const size_t lds = prim_parents_in_lds<C>() ? (size_t)2 * 1024 * C : 0;           \
+        if (lds > 0) {                                                                     \
+            const hipError_t e = hipFuncSetAttribute(                                      \
+                (const void*)tree_finish_kernel<C, WIDEST>,                                \
+                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                     \
+            if (e != hipSuccess) return e;                                                 \
+        }                                                                                  \
         APPD_LAUNCH("tree_finish_kernel", s,                                               \
-                    tree_finish_kernel<C, WIDEST><<<blocks, 1024, 0, s>>>(W, n, out, w.par, \
+                    tree_finish_kernel<C, WIDEST><<<blocks, 1024, lds, s>>>(W, n, out, w.par, \
                         w.keyup, w.link, w.size, w.gcount, w.hook, w.lb, w.ctrl));         \
         return hipGetLastError();                                                          \
     }

@@ -519,7 +519,7 @@ int appd_batch_prepare(const int32_t* ns_host, int num_graphs, void* ws, size_t 
         o += n * n;
         no += n;
         const int64_t nt = (n + tile - 1) / tile;
-        tiles += nt * nt;
+        tiles += nt * (nt + 1) / 2;  // upper-triangle tile pairs
         gch += (n + appd::kGradRows - 1) / appd::kGradRows;
         vb += (n + appd::kChainThreads - 1) / appd::kChainThreads;
         p.max_n = std::max(p.max_n, (int)n);
@@ -818,7 +818,8 @@ int appd_pairwise_euclidean(const float* X, int n, int d, float* W, void* ws, si
     const int64_t nt = (n + appd::pairwise_tile() - 1) / appd::pairwise_tile();
     hipError_t e = appd::run_scale_offsets(t.noff, 1, d, t.xoff, s);
     if (e == hipSuccess)
-        e = appd::run_pairwise(X, t.xoff, t.offsets, t.ns, t.tile_start, 1, (int)(nt * nt), d, W, s);
+        e = appd::run_pairwise(X, t.xoff, t.offsets, t.ns, t.tile_start, 1, (int)(nt * (nt + 1) / 2),
+                               d, W, s);
     return hip_status(e);
 }
 

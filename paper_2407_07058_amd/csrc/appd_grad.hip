@@ -65,17 +65,36 @@ __device__ __forceinline__ float sqrt_rn_exact(float x) {
     return sub ? s * 2.44140625e-4f : s;
 }
 
+// Tile pair (bi, bj), bi <= bj, of the b-th upper-triangle tile in row-major
+// order over an nt x nt tile grid (row bi holds nt - bi tiles).
+__device__ __forceinline__ void upper_tile(int b, int nt, int* bi, int* bj) {
+    const double tt = 2.0 * nt + 1.0;
+    int i = (int)((tt - sqrt(tt * tt - 8.0 * (double)b)) * 0.5);
+    i = i < 0 ? 0 : (i > nt - 1 ? nt - 1 : i);
+    auto start = [&](int r) { return (int64_t)r * nt - (int64_t)r * (r - 1) / 2; };
+    while (i > 0 && start(i) > b) --i;
+    while (i < nt - 1 && start(i + 1) <= b) ++i;
+    *bi = i;
+    *bj = i + (int)(b - start(i));
+}
+
+// One workgroup per upper-triangle tile pair (ti <= tj): the 64 x 64 block of
+// W at rows ti, columns tj is computed once and written there and, through an
+// LDS transpose, at rows tj, columns ti (W is bit-symmetric: the differences of
+// the mirrored pair are negations, their squares equal).
 __global__ __launch_bounds__(kPairThreads) void pairwise_kernel(
     const float* __restrict__ X, const int64_t* __restrict__ xoff,
     const int64_t* __restrict__ offsets, const int32_t* __restrict__ ns,
     const int32_t* __restrict__ tile_start, int num_graphs, int d, float* __restrict__ W) {
     __shared__ float xi[kTile][kMaxD + 1];
     __shared__ float xjT[kMaxD][kTile + 1];
+    static_assert(kMaxD >= kTile, "the transpose reuses xi as a 64 x 65 tile");
     const int g = find_item(tile_start, num_graphs, blockIdx.x);
     const int n = ns[g];
     const int nt = (n + kTile - 1) / kTile;
     const int tile = blockIdx.x - tile_start[g];
-    const int ti = tile / nt, tj = tile % nt;
+    int ti, tj;
+    upper_tile(tile, nt, &ti, &tj);
     const float* Xg = X + xoff[g];
     float* Wg = W + offsets[g];
     const int i0 = ti * kTile, j0 = tj * kTile;
@@ -87,15 +106,32 @@ __global__ __launch_bounds__(kPairThreads) void pairwise_kernel(
     __syncthreads();
     const int c = threadIdx.x & (kTile - 1);
     const int j = j0 + c;
-    for (int r = threadIdx.x / kTile; r < kTile; r += kPairThreads / kTile) {
+    constexpr int RS = kPairThreads / kTile;  // row step
+    float vals[kTile / RS];
+#pragma unroll
+    for (int k = 0; k < kTile / RS; ++k) {
+        const int r = threadIdx.x / kTile + RS * k;
         const int i = i0 + r;
+        vals[k] = 0.0f;
         if (i >= n || j >= n) continue;
         float acc = 0.0f;
         for (int t = 0; t < d; ++t) {
             const float df = __fsub_rn(xi[r][t], xjT[t][c]);
             acc = __fadd_rn(acc, __fmul_rn(df, df));
         }
-        Wg[(size_t)i * n + j] = (i == j) ? 0.0f : sqrt_rn_exact(acc);
+        vals[k] = (i == j) ? 0.0f : sqrt_rn_exact(acc);
+        Wg[(size_t)i * n + j] = vals[k];
+    }
+    if (ti == tj) return;  // workgroup-uniform: a diagonal block is its own mirror
+    __syncthreads();       // xi is read no more: it becomes the transpose tile
+#pragma unroll
+    for (int k = 0; k < kTile / RS; ++k) xi[threadIdx.x / kTile + RS * k][c] = vals[k];
+    __syncthreads();
+    const int ic = i0 + c;  // column of the mirrored block
+#pragma unroll
+    for (int k = 0; k < kTile / RS; ++k) {
+        const int jr = threadIdx.x / kTile + RS * k;  // row of the mirrored block
+        if (j0 + jr < n && ic < n) Wg[(size_t)(j0 + jr) * n + ic] = xi[c][jr];
     }
 }
 

@@ -135,18 +135,30 @@ __global__ __launch_bounds__(kPairThreads) void pairwise_kernel(
     }
 }
 
-// Slot of the tree edge with flat index e = u*n + v (u < v).
-__device__ __forceinline__ int edge_slot(uint32_t e, uint32_t n, double inv_n,
+// Columns per lane and block of a row in edge_grad_kernel, and the largest n
+// whose parents are staged in LDS beside the histogram.
+constexpr int kGradCols = 8;
+constexpr int kGradParLds = 8192;
+
+// Slot of the tree edge with flat index f = u*n + v (u < v, f < n*n): u and v
+// by a float quotient, off by at most one for n < 2^22 (the product's
+// relative error is below 2^-22 and f/n < n), then corrected.
+__device__ __forceinline__ int edge_slot(uint32_t f, int n, float rcp_n,
                                          const int32_t* __restrict__ parent) {
-    int64_t q = (int64_t)((double)e * inv_n);
-    int64_t r = (int64_t)e - q * (int64_t)n;
-    if (r < 0) { --q; r += n; }
-    if (r >= (int64_t)n) { ++q; r -= n; }
-    const int u = (int)q, v = (int)r;
+    int u = (int)((float)f * rcp_n);
+    int v = (int)f - u * n;
+    if (v < 0) { --u; v += n; }
+    else if (v >= n) { ++u; v -= n; }
     return parent[v] == u ? v : u;
 }
 
-// One workgroup: rows [r0, r1) of one graph; hist holds n floats of LDS.
+// One workgroup: rows [r0, r1) of one graph, one wave per row at a time; LDS:
+// the n-float histogram over the slots, then (PAR_LDS) the graph's parents.
+// A wave reads a block of kGradCols * 64 columns of its row with every idx
+// and G load issued before the first is used (buffer loads over the row: a
+// row of a packed graph starts at any 4-byte boundary), then adds each entry
+// to its slot's bin.
+template <bool PAR_LDS>
 __global__ __launch_bounds__(256) void edge_grad_kernel(
     const float* __restrict__ G, const int32_t* __restrict__ idx,
     const int64_t* __restrict__ offsets, const int64_t* __restrict__ noff,
@@ -159,29 +171,60 @@ __global__ __launch_bounds__(256) void edge_grad_kernel(
     const int chunk = blockIdx.x - chunk_start[g];
     const float* Gg = G + offsets[g];
     const int32_t* Ig = idx + offsets[g];
-    const int32_t* par = parent + noff[g];
-    for (int k = threadIdx.x; k < n; k += blockDim.x) hist[k] = 0.0f;
+    const int32_t* gpar = parent + noff[g];
+    int32_t* spar = reinterpret_cast<int32_t*>(hist + n);
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        hist[k] = 0.0f;
+        if (PAR_LDS) spar[k] = gpar[k];
+    }
     __syncthreads();
-    const double inv_n = 1.0 / (double)n;
+    const int32_t* par = PAR_LDS ? spar : gpar;
+    const float rcp_n = 1.0f / (float)n;
+    const uint32_t nn = (uint32_t)n * (uint32_t)n;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int r0 = chunk * rows_per_wg, r1 = min(n, r0 + rows_per_wg);
-    const size_t e0 = (size_t)r0 * n, e1 = (size_t)r1 * n;
-    int last = -1;
-    float run = 0.0f;
-    for (size_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        const int32_t f = Ig[e];
-        // the diagonal (-1), and anything that is not a flat index of this graph
-        if (f < 0 || (uint32_t)f >= (uint32_t)n * (uint32_t)n) continue;
-        const int s = edge_slot((uint32_t)f, (uint32_t)n, inv_n, par);
-        const float gv = Gg[e];
-        if (s != last) {
-            if (last >= 0) atomicAdd(&hist[last], run);
-            last = s;
-            run = gv;
-        } else {
-            run += gv;
+    for (int r = r0 + wave; r < r1; r += blockDim.x / kWave) {
+        // Most of a row's pairs share one bottleneck, nearly always the edge
+        // of the row's own vertex or of its parent (slots r and parent[r]):
+        // those two are summed in registers, so that the bins' atomics see
+        // few lanes on one address.
+        const int sa = r, sb = par[r];
+        float acc_a = 0.0f, acc_b = 0.0f;
+        const __amdgpu_buffer_rsrc_t ri = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<int32_t*>(Ig + (size_t)r * n), (short)0, n * 4, kBufferRsrcWord3);
+        const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(Gg + (size_t)r * n), (short)0, n * 4, kBufferRsrcWord3);
+        for (int c0 = 0; c0 < n; c0 += kGradCols * kWave) {
+            uint32_t f[kGradCols];
+            float gv[kGradCols];
+#pragma unroll
+            for (int e = 0; e < kGradCols; ++e) {
+                const int off = (c0 + e * kWave + lane) * 4;
+                f[e] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(ri, off, 0, 0);
+                gv[e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rg, off, 0, 0));
+            }
+#pragma unroll
+            for (int e = 0; e < kGradCols; ++e) {
+                // columns past the row, the diagonal (-1) and anything that is
+                // not a flat index of this graph add nothing
+                if (c0 + e * kWave + lane < n && f[e] < nn) {
+                    const int sl = edge_slot(f[e], n, rcp_n, par);
+                    if (sl == sa) acc_a += gv[e];
+                    else if (sl == sb) acc_b += gv[e];
+                    else atomicAdd(&hist[sl], gv[e]);
+                }
+            }
+        }
+#pragma unroll
+        for (int m = kWave / 2; m >= 1; m >>= 1) {
+            acc_a += __shfl_xor(acc_a, m);
+            acc_b += __shfl_xor(acc_b, m);
+        }
+        if (lane == 0) {
+            atomicAdd(&hist[sa], acc_a);
+            if (sb >= 0) atomicAdd(&hist[sb], acc_b);
         }
     }
-    if (last >= 0) atomicAdd(&hist[last], run);
     __syncthreads();
     float* ge = gedge + noff[g];
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
@@ -232,15 +275,21 @@ hipError_t run_edge_grad(const float* G, const int32_t* idx, const int64_t* offs
                          const int32_t* chunk_start, int num_graphs, int total_chunks,
                          int rows_per_wg, int max_n, float* gedge, hipStream_t s) {
     if (total_chunks == 0) return hipSuccess;
-    const size_t lds = sizeof(float) * (size_t)max_n;
+    const bool par_lds = max_n <= kGradParLds;
+    const size_t lds = (par_lds ? 8 : 4) * (size_t)max_n;
+    const void* fn = par_lds ? (const void*)edge_grad_kernel<true> : (const void*)edge_grad_kernel<false>;
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)edge_grad_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    APPD_LAUNCH("edge_grad_kernel", s,
-        edge_grad_kernel<<<total_chunks, 256, lds, s>>>(G, idx, offsets, noff, ns, parent,
-            chunk_start, num_graphs, rows_per_wg, gedge));
+    if (par_lds)
+        APPD_LAUNCH("edge_grad_kernel", s,
+            edge_grad_kernel<true><<<total_chunks, 256, lds, s>>>(G, idx, offsets, noff, ns, parent,
+                chunk_start, num_graphs, rows_per_wg, gedge));
+    else
+        APPD_LAUNCH("edge_grad_kernel", s,
+            edge_grad_kernel<false><<<total_chunks, 256, lds, s>>>(G, idx, offsets, noff, ns,
+                parent, chunk_start, num_graphs, rows_per_wg, gedge));
     return hipGetLastError();
 }
 

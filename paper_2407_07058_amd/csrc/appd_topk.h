@@ -7,9 +7,6 @@
 namespace appd {
 
 constexpr int kK = 16;  // candidate list length
-// Word 3 of a buffer resource on gfx9: 32-bit data format, no swizzle; with
-// stride 0 a load whose offset lies past the range returns 0.
-constexpr int kBufferRsrcWord3 = 0x00020000;
 constexpr uint64_t kTopkNone = ~0ull;
 
 // One wave per row.  Lanes 0..K-1 hold the row's K smallest entries seen so

@@ -383,6 +383,25 @@ int appd_membench_write(void* dst, size_t bytes, uint32_t value, void* stream);
 int appd_membench_chase(const uint32_t* next, uint32_t length, uint32_t start, int steps,
                         uint32_t* out, void* stream);
 
+/* ------------------------------------------------------------------ write-once check
+ * Algorithm 4's calculation and copy (Section 3) assigns every entry of M once.
+ * These run the forward (appd_forward_ex with ws and no order/parent outputs,
+ * resp. appd_forward_batched with no parent output) with every store of an
+ * output element counted: counts (device uint32, n*n resp. plan->total_nn, in
+ * the layout of M) is cleared first, then each store adds 1 to the counter of
+ * every element of M it writes and 0x10000 for idx, so an entry stored exactly
+ * once reads 0x00010001 (the diagonal included).  M and idx are the forward's
+ * outputs as usual.  For testing: the call synchronises `stream` before and
+ * after the forward and is not capturable, and the counting switch is per GPU
+ * and process, so no other forward may run on the GPU meanwhile (its stores
+ * would be counted, or fault on the counter range).  Errors as the forward's;
+ * APPD_EINVAL also for counts == NULL or (single) ws == NULL. */
+int appd_debug_write_counts(const float* W, int n, int mode, float* M, int32_t* idx,
+                            uint32_t* counts, void* ws, size_t ws_bytes, void* stream);
+int appd_debug_write_counts_batched(const float* W, int mode, float* M, int32_t* idx,
+                                    uint32_t* counts, const appd_batch_plan* plan, void* ws,
+                                    void* stream);
+
 #ifdef __cplusplus
 }
 #endif

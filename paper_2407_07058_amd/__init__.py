@@ -72,6 +72,8 @@ SIGNATURES = {
     "appd_timer_start": ([ctypes.c_char_p, _I], _I),
     "appd_timer_read": ([ctypes.c_char_p, _P, _P, _P], _I),
     "appd_timer_names": ([_P, _I], _I),
+    "appd_debug_write_counts": ([_P, _I, _I, _P, _P, _P, _P, _SZ, _P], _I),
+    "appd_debug_write_counts_batched": ([_P, _I, _P, _P, _P, _P, _P, _P], _I),
 }
 
 VALID_NAN = 0x1
@@ -249,6 +251,24 @@ def forward(W: torch.Tensor, mode: int = MINIMAX, return_tree: bool = False, out
     return M, idx
 
 
+def write_counts(W: torch.Tensor, mode: int = MINIMAX, tree: str = "auto"):
+    """(M, idx, counts): the forward with every output store counted (a check
+    that the fill writes each entry once).  counts is n x n int32 holding
+    (stores of idx) << 16 | (stores of M); synchronises the device's stream,
+    and nothing else may run on the GPU meanwhile."""
+    n = _check_square(W)
+    mode = _mode(mode, tree)
+    dev = W.device
+    M = torch.empty(n, n, dtype=torch.float32, device=dev)
+    idx = torch.empty(n, n, dtype=torch.int32, device=dev)
+    counts = torch.empty(n, n, dtype=torch.int32, device=dev)
+    ws = torch.empty(workspace_bytes(n), dtype=torch.uint8, device=dev)
+    _check(lib().appd_debug_write_counts(_ptr(W), n, int(mode), _ptr(M), _ptr(idx), _ptr(counts),
+                                         _ptr(ws), ws.numel(), _stream(dev)),
+           "appd_debug_write_counts")
+    return M, idx, counts
+
+
 def tree_stats(n: int, workspace: torch.Tensor, mode: int = MINIMAX, tree: str = "auto") -> dict:
     """What the last spanning-tree run in `workspace` did: Boruvka or Prim,
     passes over W (of which `tables` were component-table passes over its
@@ -400,6 +420,19 @@ class Batch:
                                           ctypes.byref(self.plan), _ptr(self.ws),
                                           _stream(self.device)), "appd_forward_batched")
         return (M, idx, parent) if return_parent else (M, idx)
+
+    def write_counts(self, W: torch.Tensor, mode: int = MINIMAX):
+        """Packed (M, idx, counts): the batched forward with every output store
+        counted, as write_counts() for one graph."""
+        _check_tensor(W, "W", torch.float32, self.total_nn, self.device)
+        M = torch.empty(self.total_nn, dtype=torch.float32, device=self.device)
+        idx = torch.empty(self.total_nn, dtype=torch.int32, device=self.device)
+        counts = torch.empty(self.total_nn, dtype=torch.int32, device=self.device)
+        _check(lib().appd_debug_write_counts_batched(_ptr(W), int(mode), _ptr(M), _ptr(idx),
+                                                     _ptr(counts), ctypes.byref(self.plan),
+                                                     _ptr(self.ws), _stream(self.device)),
+               "appd_debug_write_counts_batched")
+        return M, idx, counts
 
     def pairwise(self, X: torch.Tensor, d: int, out: torch.Tensor = None) -> torch.Tensor:
         """Packed Euclidean W of the batch's point sets (X: total_n x d float32)."""

@@ -2,6 +2,7 @@
 // error reporting.  All compute is enqueued by the kernels' launchers.
 #include "appd.h"
 #include "appd_internal.h"
+#include "appd_wcount.h"
 #include "appd_prim.h"
 
 namespace {
@@ -143,6 +144,31 @@ int appd_linkage(const float* W, int n, int mode, double* Z, void* ws, size_t ws
         e = appd::run_linkage(W, n, mode, appd::PrimOut{w.order, w.ek, w.pos, w.parent}, w.tree_ws,
                               Z, s);
     if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(APPD_EHIP);
+    }
+    return ok();
+}
+
+int appd_debug_write_counts(const float* W, int n, int mode, float* M, int32_t* idx,
+                            uint32_t* counts, void* ws, size_t ws_bytes, void* stream) {
+    if (bad_n(n) || !counts || !ws) return fail(APPD_EINVAL);
+    hipStream_t s = (hipStream_t)stream;
+    const appd::WriteCount on{counts, M, idx}, off{nullptr, nullptr, nullptr};
+    hipError_t e = appd::run_zero(counts, (size_t)n * (size_t)n * 4, s);
+    if (e == hipSuccess) e = appd::set_write_count_single(on, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(APPD_EHIP);
+    }
+    const int rc = appd_forward_ex(W, n, mode, M, idx, nullptr, nullptr, ws, ws_bytes, stream);
+    e = hipStreamSynchronize(s);
+    // the switch goes off whatever the forward returned
+    const hipError_t e_off = appd::set_write_count_single(off, s);
+    const hipError_t e_sync = hipStreamSynchronize(s);
+    if (rc != APPD_OK) return rc;
+    if (e != hipSuccess || e_off != hipSuccess || e_sync != hipSuccess) {
         (void)hipGetLastError();
         return fail(APPD_EHIP);
     }

@@ -12,6 +12,7 @@
 
 #include "appd.h"
 #include "appd_internal.h"
+#include "appd_wcount.h"
 
 namespace {
 
@@ -758,6 +759,33 @@ int appd_forward_batched(const float* W, int mode, float* M, int32_t* idx, int32
     appd::BatchPlan bp = device_plan(plan, t);
     return hip_status(appd::run_batched(W, t.offsets, t.ns, bp, tree, t.blk, mode, M, idx,
                                         (hipStream_t)stream));
+}
+
+int appd_debug_write_counts_batched(const float* W, int mode, float* M, int32_t* idx,
+                                    uint32_t* counts, const appd_batch_plan* plan, void* ws,
+                                    void* stream) {
+    if (!counts || !plan_ok(plan, ws)) return fail(APPD_EINVAL);
+    hipStream_t s = (hipStream_t)stream;
+    const appd::WriteCount on{counts, M, idx}, off{nullptr, nullptr, nullptr};
+    hipError_t e = appd::run_zero(counts, (size_t)plan->total_nn * 4, s);
+    if (e == hipSuccess) e = appd::set_write_count_batched(on, s);
+    if (e == hipSuccess) e = appd::set_write_count_persist(on, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(APPD_EHIP);
+    }
+    const int rc = appd_forward_batched(W, mode, M, idx, nullptr, plan, ws, stream);
+    e = hipStreamSynchronize(s);
+    const hipError_t e_off1 = appd::set_write_count_batched(off, s);
+    const hipError_t e_off2 = appd::set_write_count_persist(off, s);
+    const hipError_t e_sync = hipStreamSynchronize(s);
+    if (rc != APPD_OK) return rc;
+    if (e != hipSuccess || e_off1 != hipSuccess || e_off2 != hipSuccess || e_sync != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(APPD_EHIP);
+    }
+    return ok();
 }
 
 int appd_pairwise_euclidean_batched(const float* X, int d, float* W, const appd_batch_plan* plan,

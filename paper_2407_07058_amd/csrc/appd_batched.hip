@@ -431,4 +431,10 @@ hipError_t run_batched(const float* W, const int64_t* offsets, const int32_t* ns
                      : run_batched_t<false>(W, offsets, ns, plan, tree, blk, M, idx, s);
 }
 
+// This unit's copy of the write-count switch (appd_wcount.h).
+hipError_t set_write_count_batched(const WriteCount& wc, hipStream_t s) {
+    return hipMemcpyToSymbolAsync(HIP_SYMBOL(c_write_count), &wc, sizeof wc, 0,
+                                  hipMemcpyHostToDevice, s);
+}
+
 }  // namespace appd

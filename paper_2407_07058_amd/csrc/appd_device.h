@@ -19,6 +19,8 @@ constexpr int kWave = 64;
 // Word 3 of a buffer resource on gfx9: 32-bit data format, no swizzle; with
 // stride 0 a load whose offset lies past the range returns 0.
 constexpr int kBufferRsrcWord3 = 0x00020000;
+// Cache-policy argument of a buffer store: non-temporal (nt).
+constexpr int kBufferNontemporal = 2;
 
 __device__ __forceinline__ uint32_t ord32(float w) {
     uint32_t b = __float_as_uint(w);

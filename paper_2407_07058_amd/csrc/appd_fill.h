@@ -30,6 +30,7 @@
 #pragma once
 
 #include "appd_device.h"
+#include "appd_wcount.h"
 
 namespace appd {
 
@@ -196,6 +197,7 @@ __device__ __forceinline__ void fill_prep_block(const int32_t* __restrict__ pos,
 // 16-byte vectors for the non-temporal stores of M and idx
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef int i4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
 template <int CB, bool WIDEST, bool VEC>
 __device__ __forceinline__ void fill_rows_block(const int32_t* __restrict__ pos,
@@ -295,12 +297,16 @@ __device__ __forceinline__ void fill_rows_block(const int32_t* __restrict__ pos,
                 iv.w = k3v ? (int32_t)(uint32_t)k3v : -1;
                 *(float4*)(mrow + c) = mv;
                 *(int4*)(irow + c) = iv;
+                count_writes(mrow + c, 4);
+                count_writes(irow + c, 4);
             }
         } else {
             auto put1 = [&](int c) {
                 const uint64_t key = s_R[s_slot[c]];
                 mrow[c] = key ? key_weight<WIDEST>(key) : 0.0f;
                 irow[c] = key ? (int32_t)(uint32_t)key : -1;
+                count_writes(mrow + c, 1);
+                count_writes(irow + c, 1);
             };
             // A row may start at any 4-byte boundary (graphs packed back to
             // back).  When the M and idx rows are aligned alike: the columns
@@ -329,6 +335,8 @@ __device__ __forceinline__ void fill_rows_block(const int32_t* __restrict__ pos,
                                     k3v ? (int32_t)(uint32_t)k3v : -1};
                     __builtin_nontemporal_store(mv, (f4v*)(mrow + c));
                     __builtin_nontemporal_store(iv, (i4v*)(irow + c));
+                    count_writes(mrow + c, 4);
+                    count_writes(irow + c, 4);
                 }
             } else {
                 for (int c = lane; c < cnt; c += kWave) put1(c);
@@ -349,10 +357,10 @@ __device__ __forceinline__ void fill_rows_block(const int32_t* __restrict__ pos,
 // last-level cache, and lines left dirty there would be written back during
 // whatever runs next (the following pass over W).  s_R: this wave's row
 // buffer of CB codes; s_dM / s_dI: CB + 2 * nwaves entries.
-// EXACT (short blocks, the batched fill): the 16-byte stores cover only the
-// block's columns; otherwise every lane issues CB / 256 of them, a short block
-// repeating its last four columns, so that the count of memory operations per
-// row is fixed.
+// EXACT (short blocks, the batched fill): the lanes past a short block's
+// columns issue no stores; otherwise every lane issues CB / 256 of them (those
+// past the block are dropped by the buffer range), so that the count of memory
+// operations per row is fixed.
 template <int CB, bool WIDEST, bool VEC, bool EXACT = false>
 __device__ __forceinline__ void fill_rows_block_coded(
     const int32_t* __restrict__ pos, const uint64_t* __restrict__ ek, int n, int j0, int cnt,
@@ -524,12 +532,20 @@ __device__ __forceinline__ void fill_rows_block_coded(
         float* mrow = M + (size_t)i * (size_t)n + j0;
         int32_t* irow = idx + (size_t)i * (size_t)n + j0;
         if (VEC) {
-            // cnt is a multiple of 4; a short block repeats its last four
-            // columns (the same values to the same addresses)
+            // cnt is a multiple of 4.  Buffer stores over the block's columns:
+            // in a short block the lanes past cnt read the last four columns'
+            // entries and their stores fall outside the range and are dropped,
+            // so every lane issues the same stores and each column is written
+            // once.
+            const __amdgpu_buffer_rsrc_t rm =
+                __builtin_amdgcn_make_buffer_rsrc(mrow, (short)0, cnt * 4, kBufferRsrcWord3);
+            const __amdgpu_buffer_rsrc_t ri =
+                __builtin_amdgcn_make_buffer_rsrc(irow, (short)0, cnt * 4, kBufferRsrcWord3);
 #pragma unroll
             for (int it = 0; it < CB / (4 * kWave); ++it) {
                 if (EXACT && lane * 4 + it * 4 * kWave >= cnt) break;
-                const int c = min(lane * 4 + it * 4 * kWave, cnt - 4);
+                const int cs = lane * 4 + it * 4 * kWave;  // the columns stored
+                const int c = min(cs, cnt - 4);           // the entries read
                 const uint64_t sl = *(const uint64_t*)(s_slot + c);  // 4 slots
                 const uint32_t c0 = s_R[sl & 0xffff] & kCodeMask;
                 const uint32_t c1 = s_R[(sl >> 16) & 0xffff] & kCodeMask;
@@ -537,14 +553,22 @@ __device__ __forceinline__ void fill_rows_block_coded(
                 const uint32_t c3 = s_R[sl >> 48] & kCodeMask;
                 const f4v mv = {s_dM[c0], s_dM[c1], s_dM[c2], s_dM[c3]};
                 const i4v iv = {s_dI[c0], s_dI[c1], s_dI[c2], s_dI[c3]};
-                __builtin_nontemporal_store(mv, (f4v*)(mrow + c));
-                __builtin_nontemporal_store(iv, (i4v*)(irow + c));
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, mv), rm, cs * 4, 0,
+                                                       kBufferNontemporal);
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, iv), ri, cs * 4, 0,
+                                                       kBufferNontemporal);
+                if (cs < cnt) {
+                    count_writes(mrow + cs, 4);
+                    count_writes(irow + cs, 4);
+                }
             }
         } else {
             auto put1 = [&](int c) {
                 const uint32_t cd = s_R[s_slot[c]] & kCodeMask;
                 __builtin_nontemporal_store(s_dM[cd], mrow + c);
                 __builtin_nontemporal_store(s_dI[cd], irow + c);
+                count_writes(mrow + c, 1);
+                count_writes(irow + c, 1);
             };
             // A row may start at any 4-byte boundary (n % 4 != 0, or graphs
             // packed back to back).  When the M and idx rows are misaligned
@@ -567,6 +591,8 @@ __device__ __forceinline__ void fill_rows_block_coded(
                     const i4v iv = {s_dI[c0], s_dI[c1], s_dI[c2], s_dI[c3]};
                     __builtin_nontemporal_store(mv, (f4v*)(mrow + c));
                     __builtin_nontemporal_store(iv, (i4v*)(irow + c));
+                    count_writes(mrow + c, 4);
+                    count_writes(irow + c, 4);
                 }
             } else {
                 for (int c = lane; c < cnt; c += kWave) put1(c);

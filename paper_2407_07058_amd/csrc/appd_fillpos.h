@@ -4,6 +4,7 @@
 
 #include "appd_device.h"
 #include "appd_internal.h"
+#include "appd_wcount.h"
 
 namespace appd {
 
@@ -146,6 +147,8 @@ __device__ __forceinline__ void fill_pos_rows(const int64_t* __restrict__ offset
             const int2 e = s_mi[R[c]];
             mrow[c] = __int_as_float(e.x);
             irow[c] = e.y;
+            count_writes(mrow + c, 1);
+            count_writes(irow + c, 1);
         };
         if (mis == (int)(((uintptr_t)irow >> 2) & 3u)) {
             const int h = min(n, (4 - mis) & 3);
@@ -163,6 +166,8 @@ __device__ __forceinline__ void fill_pos_rows(const int64_t* __restrict__ offset
                 const i4v iv = {e0.y, e1.y, e2.y, e3.y};
                 *(f4v*)(mrow + c) = mv;
                 *(i4v*)(irow + c) = iv;
+                count_writes(mrow + c, 4);
+                count_writes(irow + c, 4);
             }
         } else {
             for (int c = lane; c < n; c += kWave) put1(c);

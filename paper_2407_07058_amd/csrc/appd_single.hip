@@ -192,4 +192,10 @@ hipError_t run_single(const float* W, int n, int mode, float* M, int32_t* idx,
     return run_fill(n, mode, M, idx, w, s);
 }
 
+// This unit's copy of the write-count switch (appd_wcount.h).
+hipError_t set_write_count_single(const WriteCount& wc, hipStream_t s) {
+    return hipMemcpyToSymbolAsync(HIP_SYMBOL(c_write_count), &wc, sizeof wc, 0,
+                                  hipMemcpyHostToDevice, s);
+}
+
 }  // namespace appd

@@ -82,6 +82,21 @@ def test_forward_rejects_small_or_misaligned_workspace():
     assert L.appd_forward_ws(p, 100, p, p, ctypes.c_void_p(260), need, None) == appd.APPD_EINVAL
 
 
+def test_write_count_calls_reject_bad_arguments():
+    """The write-once check rejects a missing counter array or workspace and
+    bad sizes before anything reaches the GPU."""
+    L = appd.lib()
+    p = ctypes.c_void_p(256)
+    need = L.appd_forward_workspace_bytes(100)
+    assert L.appd_debug_write_counts(p, 100, 0, p, p, None, p, need, None) == appd.APPD_EINVAL
+    assert L.appd_debug_write_counts(p, 100, 0, p, p, p, None, need, None) == appd.APPD_EINVAL
+    assert L.appd_debug_write_counts(p, 0, 0, p, p, p, p, need, None) == appd.APPD_EINVAL
+    assert L.appd_debug_write_counts(p, 46341, 0, p, p, p, p, need, None) == appd.APPD_EINVAL
+    assert L.appd_debug_write_counts_batched(p, 0, p, p, None, None, p, None) == appd.APPD_EINVAL
+    assert L.appd_debug_write_counts_batched(p, 0, p, p, p, None, p, None) == appd.APPD_EINVAL
+    assert L.appd_get_last_error() == appd.APPD_EINVAL
+
+
 def test_batch_plan_struct_layout_matches_header(tmp_path):
     """The ctypes mirror of appd_batch_plan has the C layout."""
     import subprocess

@@ -258,6 +258,11 @@ typedef struct {
                            (every class APPD_BATCH_TREE_BORUVKA, every n <= 1024); 0: one
                            launch sequence per class */
     int persist_items;  /* work items of that launch (set with persistent) */
+    int stagger;        /* 1: with more than one stream, the other classes start after the
+                           largest class's candidate-list pass (that class on Boruvka trees,
+                           not cut), so the pass has the GPU to itself and the other
+                           classes run beside its per-graph trees and fill; 0: all classes
+                           start together */
 } appd_batch_plan;
 
 /* class_tree values.  Prim: one workgroup per graph runs Prim's algorithm

@@ -104,7 +104,8 @@ class BatchPlan(ctypes.Structure):
                 ("class_vertices", ctypes.c_int * BATCH_CLASSES),
                 ("split_vertices", ctypes.c_int),
                 ("persistent", ctypes.c_int),
-                ("persist_items", ctypes.c_int)]
+                ("persist_items", ctypes.c_int),
+                ("stagger", ctypes.c_int)]
 
 _lib = None
 
@@ -359,12 +360,13 @@ class Batch:
         return ms.value
 
     def set_schedule(self, threads=None, rows=None, streams=None, split_count=None, trees=None,
-                     persistent=None):
+                     persistent=None, stagger=None):
         """Set the schedule by hand (Prim workgroup size and fill rows per item of
         each class, streams, and how many of the largest class's biggest graphs
         run on their own, -1 for a cut into halves of equal work; persistent:
-        the whole forward as one launch over a work queue); rebuilds the device
-        work tables.  Synchronises."""
+        the whole forward as one launch over a work queue; stagger: the other
+        classes start after the largest class's candidate-list pass); rebuilds
+        the device work tables.  Synchronises."""
         p = self.plan
         for c in range(BATCH_CLASSES):
             if threads is not None:
@@ -380,6 +382,8 @@ class Batch:
             p.split_count = int(split_count)
         if persistent is not None:
             p.persistent = int(bool(persistent))
+        if stagger is not None:
+            p.stagger = int(bool(stagger))
         _check(lib().appd_batch_set_schedule(ctypes.byref(p), _ptr(self.ws), _stream(self.device)),
                "appd_batch_set_schedule")
 
@@ -407,7 +411,7 @@ class Batch:
                 "class_rows": list(p.class_rows), "streams": p.streams,
                 "split_count": p.split_count,
                 "class_tree": [names.get(x, x) for x in p.class_tree],
-                "persistent": int(p.persistent)}
+                "persistent": int(p.persistent), "stagger": int(p.stagger)}
 
     def forward(self, W: torch.Tensor, mode: int = MINIMAX, return_parent: bool = False,
                 out=None):

@@ -140,6 +140,7 @@ appd::BatchPlan device_plan(const appd_batch_plan* p, const Tables& t) {
     bp.split_vertices = p->split_vertices;
     bp.persistent = p->persistent;
     bp.persist_items = p->persist_items;
+    bp.stagger = p->stagger;
     bp.num_graphs = p->num_graphs;
     bp.total_n = (int)p->total_n;
     bp.items = t.items;
@@ -205,6 +206,7 @@ bool schedule_ok(const appd_batch_plan* p) {
             return false;
     }
     if (p->persistent != 0 && p->persistent != 1) return false;
+    if (p->stagger != 0 && p->stagger != 1) return false;
     if (p->persistent && !persistent_ok(p)) return false;
     if (p->persistent &&
         (p->persist_items < 1 || (size_t)p->persist_items > items_capacity(p->num_graphs, p->total_n)))
@@ -325,7 +327,7 @@ constexpr int kTuneReps = 5;  // timed forwards per candidate (the median counts
 
 // What a schedule sets (split: the cut argument of build_chunks, 0 or -1).
 struct TuneEntry {
-    int streams = 1, split = 0, persistent = 0;
+    int streams = 1, split = 0, persistent = 0, stagger = 0;
     int rows[appd::kBatchClasses] = {};
     int tree[appd::kBatchClasses] = {};
     int threads[appd::kBatchClasses] = {};
@@ -337,6 +339,7 @@ TuneEntry entry_of(const appd_batch_plan* p) {
     e.streams = p->streams;
     e.split = p->split_count ? -1 : 0;
     e.persistent = p->persistent;
+    e.stagger = p->stagger;
     for (int c = 0; c < appd::kBatchClasses; ++c) {
         e.rows[c] = p->class_rows[c];
         e.tree[c] = p->class_tree[c];
@@ -348,6 +351,7 @@ TuneEntry entry_of(const appd_batch_plan* p) {
 void apply_entry(const TuneEntry& e, appd_batch_plan* p) {
     p->streams = e.streams;
     p->persistent = e.persistent;
+    p->stagger = e.stagger;
     for (int c = 0; c < appd::kBatchClasses; ++c) {
         p->class_rows[c] = e.rows[c];
         p->class_tree[c] = e.tree[c];
@@ -372,13 +376,13 @@ std::string tune_key(const appd_batch_plan* p) {
 }
 
 // The cache file is one JSON object, one entry per line:
-//   "key": {"streams": 3, "split": -1, "persistent": 0, "rows": [...6],
+//   "key": {"streams": 3, "split": -1, "persistent": 0, "stagger": 1, "rows": [...6],
 //           "trees": [...6], "threads": [...6], "ms": 1.234}
 std::string entry_line(const std::string& key, const TuneEntry& e) {
     char buf[512];
     std::string r = "\"" + key + "\": {";
-    snprintf(buf, sizeof buf, "\"streams\": %d, \"split\": %d, \"persistent\": %d", e.streams, e.split,
-             e.persistent);
+    snprintf(buf, sizeof buf, "\"streams\": %d, \"split\": %d, \"persistent\": %d, \"stagger\": %d",
+             e.streams, e.split, e.persistent, e.stagger);
     r += buf;
     const int* arr[3] = {e.rows, e.tree, e.threads};
     const char* names[3] = {"rows", "trees", "threads"};
@@ -397,11 +401,11 @@ bool parse_entry(const std::string& line, std::string* key, TuneEntry* e) {
     if (q1 == std::string::npos) return false;
     *key = line.substr(q0 + 1, q1 - q0 - 1);
     const char* s = line.c_str() + q1 + 1;
-    int v[3 + 3 * appd::kBatchClasses];
+    int v[4 + 3 * appd::kBatchClasses];
     float ms = 0.f;
     int used = 0;
-    if (sscanf(s, ": {\"streams\": %d, \"split\": %d, \"persistent\": %d%n", &v[0], &v[1], &v[2],
-               &used) != 3)
+    if (sscanf(s, ": {\"streams\": %d, \"split\": %d, \"persistent\": %d, \"stagger\": %d%n", &v[0],
+               &v[1], &v[2], &v[3], &used) != 4)
         return false;
     s += used;
     const char* names[3] = {"rows", "trees", "threads"};
@@ -410,7 +414,7 @@ bool parse_entry(const std::string& line, std::string* key, TuneEntry* e) {
         if (strncmp(s, head.c_str(), head.size()) != 0) return false;
         s += head.size();
         for (int c = 0; c < appd::kBatchClasses; ++c) {
-            if (sscanf(s, c ? ", %d%n" : "%d%n", &v[3 + a * appd::kBatchClasses + c], &used) != 1)
+            if (sscanf(s, c ? ", %d%n" : "%d%n", &v[4 + a * appd::kBatchClasses + c], &used) != 1)
                 return false;
             s += used;
         }
@@ -420,10 +424,11 @@ bool parse_entry(const std::string& line, std::string* key, TuneEntry* e) {
     e->streams = v[0];
     e->split = v[1];
     e->persistent = v[2];
+    e->stagger = v[3];
     for (int c = 0; c < appd::kBatchClasses; ++c) {
-        e->rows[c] = v[3 + c];
-        e->tree[c] = v[3 + appd::kBatchClasses + c];
-        e->threads[c] = v[3 + 2 * appd::kBatchClasses + c];
+        e->rows[c] = v[4 + c];
+        e->tree[c] = v[4 + appd::kBatchClasses + c];
+        e->threads[c] = v[4 + 2 * appd::kBatchClasses + c];
     }
     e->ms = ms;
     return true;
@@ -648,21 +653,24 @@ int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan*
         return true;
     };
     // 1. the launch forms with 16 rows per fill item everywhere and Boruvka
-    //    trees: classes in order, on 3 or 4 streams (with and without the cut
-    //    of the largest class), and the persistent launch
+    //    trees: classes in order, on 3 or 4 streams (all starting at once,
+    //    staggered after the largest class's pass, or with the largest class
+    //    cut), and the persistent launch
     TuneEntry base = entry_of(plan);
     for (int c = 0; c < appd::kBatchClasses; ++c) {
         base.rows[c] = 16;
         base.tree[c] = APPD_BATCH_TREE_BORUVKA;
     }
     base.persistent = 0;
+    base.stagger = 0;
     static const int streams_opt[3] = {1, 3, 4};
     for (int si = 0; si < 3; ++si)
-        for (int sp = 0; sp < 2; ++sp) {
-            if (sp && streams_opt[si] == 1) continue;  // a cut needs two streams
+        for (int form = 0; form < 3; ++form) {  // 0: at once, 1: staggered, 2: cut
+            if (form && streams_opt[si] == 1) continue;  // both need two streams
             TuneEntry c = base;
             c.streams = streams_opt[si];
-            c.split = sp ? -1 : 0;
+            c.stagger = form == 1;
+            c.split = form == 2 ? -1 : 0;
             if (!consider(c)) return hip_fail();
         }
     {
@@ -694,6 +702,13 @@ int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan*
                 if (!consider(x)) return hip_fail();
             }
     }
+    // 3. the other start of the classes for the schedule found (the trees
+    //    chosen per class change what runs beside the largest class)
+    if (best.streams > 1 && !best.split && !best.persistent) {
+        TuneEntry x = best;
+        x.stagger = !best.stagger;
+        if (!consider(x)) return hip_fail();
+    }
     for (hipEvent_t& x : ev) {
         (void)hipEventDestroy(x);
         x = nullptr;
@@ -712,7 +727,7 @@ int appd_batch_autotune(const float* W, float* M, int32_t* idx, appd_batch_plan*
 int appd_batch_set_schedule(appd_batch_plan* plan, void* ws, void* stream) {
     if (!plan_ok(plan, ws) || plan->streams < 1 || plan->streams > appd::kBatchClasses ||
         plan->split_count < -1 || (plan->persistent != 0 && plan->persistent != 1) ||
-        (plan->persistent && !persistent_ok(plan)))
+        (plan->stagger != 0 && plan->stagger != 1) || (plan->persistent && !persistent_ok(plan)))
         return fail(APPD_EINVAL);
     for (int c = 0; c < appd::kBatchClasses; ++c) {
         if (!plan->class_count[c]) continue;

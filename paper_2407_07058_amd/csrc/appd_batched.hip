@@ -366,11 +366,23 @@ static hipError_t run_batched_t(const float* W, const int64_t* offsets, const in
     if (nstreams > 1) {
         fork_lock.lock();
         if ((e = side_streams(&ss)) != hipSuccess) return e;
+        for (int k = 1; k < nstreams; ++k) st[k] = ss->side[k - 1];
+    }
+    // Staggered: the fork is recorded after the largest class's candidate-list
+    // pass, which then streams its W with the GPU to itself, and the other
+    // classes run beside that class's per-graph trees (bound by latency) and
+    // its fill.  Otherwise every class starts at once.
+    const bool stagger = nstreams > 1 && plan.stagger && plan.split_count <= 0 &&
+                         plan.class_tree[cls[0]] == APPD_BATCH_TREE_BORUVKA;
+    auto fork = [&]() -> hipError_t {
+        hipError_t fe;
+        for (int k = 1; k < nstreams; ++k)
+            if ((fe = hipStreamWaitEvent(st[k], ss->fork, 0)) != hipSuccess) return fe;
+        return hipSuccess;
+    };
+    if (nstreams > 1 && !stagger) {
         if ((e = hipEventRecord(ss->fork, s)) != hipSuccess) return e;
-        for (int k = 1; k < nstreams; ++k) {
-            st[k] = ss->side[k - 1];
-            if ((e = hipStreamWaitEvent(st[k], ss->fork, 0)) != hipSuccess) return e;
-        }
+        if ((e = fork()) != hipSuccess) return e;
     }
     // The largest class (the longest Prim chains and most of the entries) has
     // the caller's stream to itself; the others take the side streams in turn,
@@ -388,7 +400,8 @@ static hipError_t run_batched_t(const float* W, const int64_t* offsets, const in
         auto trees = [&](int f0, int cnt, int rows_bound, hipStream_t cs) -> hipError_t {
             return plan.class_tree[c] == APPD_BATCH_TREE_BORUVKA
                        ? launch_btree(c, f0, cnt, rows_bound, WIDEST ? 1 : 0, W, offsets, ns, plan,
-                                      tree, blk, plan.lists, cs)
+                                      tree, blk, plan.lists, cs,
+                                      stagger && j == 0 ? ss->fork : nullptr)
                        : launch_prim_class<WIDEST>(c, plan.class_threads[c], f0, cnt, W, offsets,
                                                    ns, plan, tree, cs);
         };
@@ -410,6 +423,7 @@ static hipError_t run_batched_t(const float* W, const int64_t* offsets, const in
             (j == 0 || nstreams == 1) ? st[0] : st[others0 + (j - 1) % (nstreams - others0)];
         e = trees(first, count, plan.class_vertices[c], cs);
         if (e != hipSuccess) return e;
+        if (stagger && j == 0 && (e = fork()) != hipSuccess) return e;
         e = launch_fill_class<WIDEST>(c, first, count, 0, chunks, rows, offsets, ns, plan, tree,
                                       blk, M, idx, cs);
         if (e != hipSuccess) return e;

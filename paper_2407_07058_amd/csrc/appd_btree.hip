@@ -70,7 +70,7 @@ template <bool WIDEST>
 hipError_t launch_btree_t(int c, int first, int count, int rows_in_class, const float* W,
                           const int64_t* offsets, const int32_t* ns, const BatchPlan& plan,
                           const BatchTree& tree, const BatchBlk& blk, uint64_t* lists,
-                          hipStream_t s) {
+                          hipStream_t s, hipEvent_t after_pass) {
     if (count <= 0) return hipSuccess;
     const int nmax = kClassMaxN[c];
     const int blocks = (rows_in_class + kBtPassThreads / kWave - 1) / (kBtPassThreads / kWave);
@@ -89,6 +89,8 @@ hipError_t launch_btree_t(int c, int first, int count, int rows_in_class, const 
 #undef APPD_BT_PASS
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // the point other streams may wait for: the class's lists are written
+    if (after_pass && (e = hipEventRecord(after_pass, s)) != hipSuccess) return e;
     const size_t lds = btree_lds_bytes(nmax);
     // workgroup size: 256 threads, 1024 for the largest class (few graphs of
     // up to 2048 vertices: the per-graph latency is the launch's time)
@@ -119,11 +121,11 @@ hipError_t launch_btree_t(int c, int first, int count, int rows_in_class, const 
 hipError_t launch_btree(int c, int first, int count, int rows_in_class, int mode, const float* W,
                         const int64_t* offsets, const int32_t* ns, const BatchPlan& plan,
                         const BatchTree& tree, const BatchBlk& blk, uint64_t* lists,
-                        hipStream_t s) {
+                        hipStream_t s, hipEvent_t after_pass) {
     return mode == 1 ? launch_btree_t<true>(c, first, count, rows_in_class, W, offsets, ns, plan,
-                                            tree, blk, lists, s)
+                                            tree, blk, lists, s, after_pass)
                      : launch_btree_t<false>(c, first, count, rows_in_class, W, offsets, ns, plan,
-                                             tree, blk, lists, s);
+                                             tree, blk, lists, s, after_pass);
 }
 
 }  // namespace appd

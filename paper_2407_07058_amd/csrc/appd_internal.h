@@ -114,6 +114,7 @@ struct BatchPlan {
     // the persistent form (see appd_persist.hip)
     int persistent;
     int persist_items;
+    int stagger;  // the other classes' streams start after the largest class's pass
     int num_graphs;
     int total_n;
     const uint2* items;  // [persist_items] work queue (device)
@@ -124,7 +125,7 @@ int batch_class_of(int n);
 hipError_t launch_btree(int c, int first, int count, int rows_in_class, int mode, const float* W,
                         const int64_t* offsets, const int32_t* ns, const BatchPlan& plan,
                         const BatchTree& tree, const BatchBlk& blk, uint64_t* lists,
-                        hipStream_t s);
+                        hipStream_t s, hipEvent_t after_pass = nullptr);
 bool batch_threads_ok(int c, int threads);
 hipError_t run_batched(const float* W, const int64_t* offsets, const int32_t* ns,
                        const BatchPlan& plan, const BatchTree& tree, const BatchBlk& blk,

@@ -179,11 +179,18 @@ def test_batched_schedules_identical():
     wide = [64, 128, 256, 512, 512, 1024]
     mid = [64, 128, 128, 128, 512, 512]
     b = appd.Batch(ns, DEV)
-    for threads, rows, streams in [(narrow, 16, 1), (wide, 32, 3), (mid, 7, 6), (wide, 64, 2)]:
-        b.set_schedule(threads=threads, rows=rows, streams=streams, split_count=0)
+    for threads, rows, streams, stagger in [(narrow, 16, 1, 0), (wide, 32, 3, 0), (mid, 7, 6, 0),
+                                            (wide, 64, 2, 0), (narrow, 16, 4, 1), (mid, 7, 3, 1)]:
+        b.set_schedule(threads=threads, rows=rows, streams=streams, split_count=0, stagger=stagger)
         M, I = b.forward(Wd)
         torch.cuda.synchronize()
-        assert torch.equal(M, M0) and torch.equal(I, I0), (threads, rows, streams)
+        assert torch.equal(M, M0) and torch.equal(I, I0), (threads, rows, streams, stagger)
+    # staggered with the largest class on Prim workgroups: the classes start at once
+    b.set_schedule(threads=narrow, rows=16, streams=3, stagger=1, trees="prim")
+    M, I = b.forward(Wd)
+    torch.cuda.synchronize()
+    assert torch.equal(M, M0) and torch.equal(I, I0)
+    b.set_schedule(trees="boruvka", stagger=0)
     # a field edited behind the work tables' back is rejected before any launch
     b.plan.class_rows[0] += 1
     with pytest.raises(appd.APPDError):
@@ -333,11 +340,12 @@ def test_batched_autotune_plan_cache(tmp_path, monkeypatch):
     (key, entry), = data.items()
     assert "classes" in key and abs(entry["ms"] - ms1) < 1e-3
     assert entry["streams"] == b1.plan.streams and entry["persistent"] == b1.plan.persistent
+    assert entry["stagger"] == b1.plan.stagger
     b2 = appd.Batch(ns, DEV)
     ms2 = b2.autotune(Wd)
     assert abs(ms2 - entry["ms"]) < 1e-3
     s1, s2 = b1.schedule(), b2.schedule()
-    for k in ("class_rows", "class_tree", "streams", "persistent"):
+    for k in ("class_rows", "class_tree", "streams", "persistent", "stagger"):
         assert s1[k] == s2[k], k
     M, idx = b2.forward(Wd)
     torch.cuda.synchronize()
@@ -348,14 +356,16 @@ def test_batched_autotune_plan_cache(tmp_path, monkeypatch):
         assert np.array_equal(Ms[g].view(np.uint32), Mo.view(np.uint32)) and np.array_equal(Is[g], io), g
 
 
-def test_batched_streams_graph_capture_replays():
-    """Classes on concurrent library streams (fork/join events) inside a HIP
-    graph: every replay equals the eager result."""
-    say("case batched streams + HIP graph capture")
+@pytest.mark.parametrize("stagger", [0, 1])
+def test_batched_streams_graph_capture_replays(stagger):
+    """Classes on concurrent library streams (fork/join events; staggered: the
+    fork after the largest class's pass) inside a HIP graph: every replay
+    equals the eager result."""
+    say("case batched streams + HIP graph capture stagger=%d" % stagger)
     Ws = mixed_graphs(8)
     flat, offsets, ns = workloads.pack(Ws)
     b = appd.Batch(ns, DEV)
-    b.set_schedule(threads=[64, 128, 256, 512, 512, 1024], rows=16, streams=4)
+    b.set_schedule(threads=[64, 128, 256, 512, 512, 1024], rows=16, streams=4, stagger=stagger)
     Wd = torch.from_numpy(flat).to(DEV)
     M0, I0 = b.forward(Wd)
     torch.cuda.synchronize()

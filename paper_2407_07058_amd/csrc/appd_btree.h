@@ -14,6 +14,7 @@ namespace appd {
 
 constexpr int kBtRefreshes = 8;      // refreshes of a stuck graph's lists before Prim
 constexpr int kBtK = 16;             // candidate list length
+constexpr int kBtPre = 4;            // list entries per vertex read ahead in a round
 constexpr uint16_t kNil16 = 0xffff;
 
 // Block-wide exclusive scan over NT threads; s: NT / 64 ints.
@@ -84,10 +85,99 @@ __device__ __forceinline__ BtLds bt_carve(void* base, int nmax) {
     return L;
 }
 
+// The same sort with E = N / NT elements per thread held in registers:
+// element t * E + r sits in register r of thread t, so the stages whose
+// stride is below E run in registers, those below 64 E exchange with another
+// lane of the wave (no barrier), and only strides of 64 E and above go
+// through LDS with two barriers.  Equal keys (the padding) stay where they
+// are, so the payloads remain a permutation.
+template <int NT, int E, class K>
+__device__ __forceinline__ void bt_bitonic_regs(K* key, uint16_t* pay, int N) {
+    const int t = threadIdx.x, lane = t & (kWave - 1);
+    const int base = t * E;
+    __syncthreads();
+    K k[E];
+    uint32_t p[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        k[r] = key[base + r];
+        p[r] = pay[base + r];
+    }
+    for (int size = 2; size <= N; size <<= 1) {
+        // strides across waves, through LDS
+        for (int stride = size >> 1; stride >= kWave * E; stride >>= 1) {
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                key[base + r] = k[r];
+                pay[base + r] = (uint16_t)p[r];
+            }
+            __syncthreads();
+            const int pb = base ^ stride;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const K o = key[pb + r];
+                const uint32_t po = pay[pb + r];
+                const int idx = base + r;
+                const bool up = (idx & size) == 0, lower = (idx & stride) == 0;
+                if (lower == up ? o < k[r] : o > k[r]) {
+                    k[r] = o;
+                    p[r] = po;
+                }
+            }
+            __syncthreads();
+        }
+        // strides across the lanes of a wave
+        for (int stride = min(size >> 1, kWave * E / 2); stride >= E; stride >>= 1) {
+            const int lm = stride / E;
+            const bool lower = (lane & lm) == 0;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                const K o = __shfl_xor(k[r], lm);
+                const uint32_t po = (uint32_t)__shfl_xor((int)p[r], lm);
+                const bool up = ((base + r) & size) == 0;
+                if (lower == up ? o < k[r] : o > k[r]) {
+                    k[r] = o;
+                    p[r] = po;
+                }
+            }
+        }
+        // strides within a thread's registers
+#pragma unroll
+        for (int s = E / 2; s >= 1; s >>= 1) {
+            if (s > (size >> 1)) continue;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                if (r & s) continue;
+                const int q = r | s;
+                const bool up = ((base + r) & size) == 0;
+                if ((k[r] > k[q]) == up) {
+                    const K kx = k[r];
+                    k[r] = k[q];
+                    k[q] = kx;
+                    const uint32_t px = p[r];
+                    p[r] = p[q];
+                    p[q] = px;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        key[base + r] = k[r];
+        pay[base + r] = (uint16_t)p[r];
+    }
+    __syncthreads();
+}
+
 // Ascending bitonic sort of key[0 .. N) (N a power of two) with a 16-bit
 // payload, by the NT threads of the workgroup.
 template <int NT, class K>
 __device__ __forceinline__ void bt_bitonic(K* key, uint16_t* pay, int N) {
+    if (N == NT) return bt_bitonic_regs<NT, 1>(key, pay, N);
+    if (N == 2 * NT) return bt_bitonic_regs<NT, 2>(key, pay, N);
+    if (N == 4 * NT) return bt_bitonic_regs<NT, 4>(key, pay, N);
+    if (N == 8 * NT) return bt_bitonic_regs<NT, 8>(key, pay, N);
+    // fewer keys than threads: one compare-exchange per thread and stage
     for (int size = 2; size <= N; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             __syncthreads();
@@ -144,16 +234,19 @@ struct BtAux {
     int32_t* red_v;     // 2 * NT / 64
     int* wsum;          // NT / 64
     int* flag;          // 4
+    uint64_t* wbuf;     // 128 per wave: the refresh's candidate buffers
 };
 
 template <int NT>
 __host__ __device__ constexpr size_t bt_aux_bytes() {
-    return 8 * (2 * NT / 64) + 4 * (2 * NT + 2 * NT / 64 + NT / 64 + 4);
+    return 8 * (128 * (NT / 64) + 2 * NT / 64) + 4 * (2 * NT + 2 * NT / 64 + NT / 64 + 4);
 }
 
 template <int NT>
 __device__ __forceinline__ BtAux bt_aux_carve(char* p) {
     BtAux a;
+    a.wbuf = (uint64_t*)p;
+    p += 8 * 128 * (NT / 64);
     a.red_key = (uint64_t*)p;
     p += 8 * (2 * NT / 64);
     a.segv = (int*)p;
@@ -224,12 +317,35 @@ __device__ __forceinline__ void bt_finish_graph(
             for (int d = t; d < C; d += NT) L.a8[d] = L.b8[d] = kTopkNone;
             if (t == 0) s_flag[0] = 0;
             __syncthreads();
-            for (int v = t; v < n; v += NT) {
+            // A vertex's scan from its list pointer: `pre` holds the entries
+            // at p .. p + PRE - 1 (read before), further ones are read eight
+            // at a time.  (Fewer read ahead in 1024-thread workgroups, whose
+            // threads have 128 registers.)
+            constexpr int PRE = NT >= 1024 ? 1 : kBtPre;
+            auto scan = [&](int v, int p, const uint64_t (&pre)[PRE]) {
                 const int cv = L.comp[v];
                 const uint64_t* lv = lists + (size_t)v * kBtK;
-                int p = L.lptr[v];
                 int state = 0;  // 0 searching, 1 external entry at p, 2 list ended, 3 used up
                 uint64_t e = kTopkNone;
+#pragma unroll
+                for (int j = 0; j < PRE; ++j) {
+                    if (state != 0) continue;
+                    if (p + j >= kBtK) {
+                        state = 3;
+                        continue;
+                    }
+                    const uint64_t x = pre[j];
+                    if ((uint32_t)x >= un) {  // end of the list (or not a vertex)
+                        state = 2;
+                        p += j;
+                    } else if ((int)L.comp[(uint32_t)x] != cv) {
+                        state = 1;
+                        e = x;
+                        p += j;
+                    }
+                }
+                if (state == 0) p += PRE;
+                if (state == 3) p = kBtK;
                 while (state == 0) {
                     if (p >= kBtK) {
                         state = 3;
@@ -246,7 +362,7 @@ __device__ __forceinline__ void bt_finish_graph(
                             continue;
                         }
                         const uint64_t x = w[j];
-                        if ((uint32_t)x >= un) {  // end of the list (or not a vertex)
+                        if ((uint32_t)x >= un) {
                             state = 2;
                             p += j;
                         } else if ((int)L.comp[(uint32_t)x] != cv) {
@@ -271,6 +387,32 @@ __device__ __forceinline__ void bt_finish_graph(
                     atomicMin((unsigned long long*)&L.b8[cv], (unsigned long long)k);
                 }
                 // state 2: the list held every eligible entry of the row: no bound
+            };
+            // the first entries of all of this thread's vertices are read
+            // before any is checked (one memory latency per round, not one per
+            // vertex); 1024-thread workgroups take their vertices one by one
+            constexpr int CHP = NT >= 1024 ? 0 : CH;  // vertices read ahead together
+            if constexpr (CHP > 0) {
+                uint64_t pre[CHP][PRE];
+                int p0[CHP];
+#pragma unroll
+                for (int c = 0; c < CHP; ++c) {
+                    const int v = min(t + c * NT, n - 1);
+                    p0[c] = L.lptr[v];
+                    const uint64_t* lv = lists + (size_t)v * kBtK;
+#pragma unroll
+                    for (int j = 0; j < PRE; ++j) pre[c][j] = lv[min(p0[c] + j, kBtK - 1)];
+                }
+#pragma unroll
+                for (int c = 0; c < CHP; ++c)
+                    if (t + c * NT < n) scan(t + c * NT, p0[c], pre[c]);
+            }
+            for (int v = t + CHP * NT; v < n; v += NT) {
+                uint64_t pv[PRE];
+                const int p = L.lptr[v];
+#pragma unroll
+                for (int j = 0; j < PRE; ++j) pv[j] = lists[(size_t)v * kBtK + min(p + j, kBtK - 1)];
+                scan(v, p, pv);
             }
             __syncthreads();
             // 2. decide: hook when the best candidate beats every bound
@@ -306,12 +448,34 @@ __device__ __forceinline__ void bt_finish_graph(
                 for (int d = t; d < C; d += NT) atomicMin(&s_flag[2], (L.d4[d] << 16) | d);
                 __syncthreads();
                 const int sc = s_flag[2] & 0xffff;
+                // Only its used-up vertices (every list entry inside the
+                // component) need new lists: a vertex whose pointer stopped
+                // earlier holds its cheapest outgoing edge (or has none).
                 for (int u = wid; u < n; u += NW) {  // u wave-uniform
-                    if ((int)L.comp[u] != sc) continue;
+                    if ((int)L.comp[u] != sc || L.lptr[u] < kBtK) continue;
                     constexpr int kRefE = NT * CH / 64 < 4 ? 4 : (NT * CH / 64 > 32 ? 32 : NT * CH / 64);
-                    const uint64_t mine = row_topk<WIDEST, true, false, kRefE, kBtK>(
-                        W + (size_t)u * n, n, u, [&](int c) { return (int)L.comp[c]; },
-                        [](int) { return make_int4(0, 0, 0, 0); });
+                    // the row's entries inside the component become NaN (never
+                    // a candidate), then its 16 smallest by rank; a row with
+                    // too many candidates under the threshold (heavy ties), and
+                    // every row in 1024-thread workgroups (128 registers),
+                    // takes the insertion list instead
+                    bool have = false;
+                    uint64_t mine = kTopkNone;
+                    if constexpr (NT < 1024) {
+                        float xr[kRefE];
+                        rank_row_load<kRefE>(W + (size_t)u * n, n, xr);
+#pragma unroll
+                        for (int e = 0; e < kRefE; ++e) {
+                            const int col = e * kWave + lane;
+                            if (col < n && (int)L.comp[col] == sc) xr[e] = __builtin_nanf("");
+                        }
+                        have = row_topk_rank_vals<WIDEST, kRefE, kBtK>(xr, n, u, aux.wbuf + wid * 128,
+                                                                        &mine);
+                    }
+                    if (!have)
+                        mine = row_topk<WIDEST, true, false, kRefE, kBtK>(
+                            W + (size_t)u * n, n, u, [&](int c) { return (int)L.comp[c]; },
+                            [](int) { return make_int4(0, 0, 0, 0); });
                     if (lane < kBtK) lists[(size_t)u * kBtK + lane] = mine;
                     if (lane == 0) L.lptr[u] = 0;
                 }

@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kBatchFillThreads) void fill_coded_batched_kernel(
     __shared__ uint64_t s_sorted[CB];
     __shared__ float s_dM[CB + 2 * NWV];
     __shared__ int32_t s_dI[CB + 2 * NWV];
-    __shared__ uint32_t s_R[NWV][CB];
+    __shared__ uint16_t s_R[NWV][CB];  // slot part of each column's code
     // graph and row chunk as in fill_batched_kernel; blockIdx.y = column block
     const int b = chunk_base + (int)blockIdx.x;
     int lo = 0, hi = count - 1;
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kBatchFillThreads) void fill_coded_batched_kernel(
     float* Mg = M + offsets[g];
     int32_t* Ig = idx + offsets[g];
     const bool vec = (n % 4 == 0) && ((((uintptr_t)Mg) | ((uintptr_t)Ig)) & 15u) == 0;
-    uint32_t* row_buf = s_R[threadIdx.x / kWave];
+    uint16_t* row_buf = s_R[threadIdx.x / kWave];
     if (vec)
         fill_rows_block_coded<CB, WIDEST, true, true>(tree.pos + o, tree.ek + o, n, j0, cnt, r0, r1, s_sp,
                                                 s_slot, blk.code + o + j0, s_sorted, s_dM, s_dI,

@@ -356,7 +356,8 @@ __device__ __forceinline__ void fill_rows_block(const int32_t* __restrict__ pos,
 // written with non-temporal stores: n^2 outputs are far larger than the
 // last-level cache, and lines left dirty there would be written back during
 // whatever runs next (the following pass over W).  s_R: this wave's row
-// buffer of CB codes; s_dM / s_dI: CB + 2 * nwaves entries.
+// buffer, the slot part (low kCodeShift bits) of each column's code, which is
+// all the decode reads; s_dM / s_dI: CB + 2 * nwaves entries.
 // EXACT (short blocks, the batched fill): the lanes past a short block's
 // columns issue no stores; otherwise every lane issues CB / 256 of them (those
 // past the block are dropped by the buffer range), so that the count of memory
@@ -366,7 +367,7 @@ __device__ __forceinline__ void fill_rows_block_coded(
     const int32_t* __restrict__ pos, const uint64_t* __restrict__ ek, int n, int j0, int cnt,
     int r0, int r1, const uint16_t* s_sp, const uint16_t* s_slot,
     const uint32_t* __restrict__ code, const uint64_t* s_sorted, float* s_dM, int32_t* s_dI,
-    uint32_t* s_R, float* __restrict__ M,
+    uint16_t* s_R, float* __restrict__ M,
     int32_t* __restrict__ idx, int nwaves) {
     constexpr int S = CB / kWave;
     static_assert(S >= 1 && S <= kWave, "CB must be in [64, 4096]");
@@ -523,10 +524,12 @@ __device__ __forceinline__ void fill_rows_block_coded(
         if (above || lane < sd) {
             const uint32_t in = above ? up_in : dn_in;
 #pragma unroll
-            for (int q = 0; q < S; ++q) s_R[k0 + q] = max(above ? pre[q] : suf[q], in);
+            for (int q = 0; q < S; ++q)
+                s_R[k0 + q] = (uint16_t)(max(above ? pre[q] : suf[q], in) & kCodeMask);
         }
-        if (lane < 16 && su < kWave && su * S + j >= ks) s_R[su * S + j] = xu;
-        if (lane >= 16 && lane < 32 && sd >= 0 && sd * S + j < ks) s_R[sd * S + j] = xd;
+        if (lane < 16 && su < kWave && su * S + j >= ks) s_R[su * S + j] = (uint16_t)(xu & kCodeMask);
+        if (lane >= 16 && lane < 32 && sd >= 0 && sd * S + j < ks)
+            s_R[sd * S + j] = (uint16_t)(xd & kCodeMask);
         wave_lds_sync();
 
         float* mrow = M + (size_t)i * (size_t)n + j0;

@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kFillThreads) void fill_kernel(const int32_t* __res
     __shared__ uint64_t s_sorted[CB];
     __shared__ float s_dM[CB + 2 * NWV];
     __shared__ int32_t s_dI[CB + 2 * NWV];
-    __shared__ uint32_t s_R[NWV][CB];
+    __shared__ uint16_t s_R[NWV][CB];  // slot part of each column's code
     const int j0 = blockIdx.x * CB;
     const int cnt = min(CB, n - j0);
     for (int k = threadIdx.x; k < CB; k += kFillThreads) {

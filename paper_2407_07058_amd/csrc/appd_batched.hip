@@ -385,12 +385,14 @@ static hipError_t run_batched_t(const float* W, const int64_t* offsets, const in
         if ((e = fork()) != hipSuccess) return e;
     }
     // The largest class (the longest Prim chains and most of the entries) has
-    // the caller's stream to itself; the others take the side streams in turn,
-    // so that they finish while it still runs.  Split, the largest class's
+    // the caller's stream to itself; each other class, largest first, takes
+    // the side stream with the least work so far, so that they finish while
+    // it still runs.  Split, the largest class's
     // biggest graphs keep the caller's stream, the rest of it takes the first
     // side stream, and the other classes the side streams after it.
     const bool split = nstreams >= 2 && plan.split_count > 0;
     const int others0 = split && nstreams >= 3 ? 2 : 1;
+    double load[kBatchClasses] = {};
     for (int j = 0; j < nc; ++j) {
         const int c = cls[j];
         const int first = plan.class_first[c], count = plan.class_count[c];
@@ -419,8 +421,18 @@ static hipError_t run_batched_t(const float* W, const int64_t* offsets, const in
             if (e != hipSuccess) return e;
             continue;
         }
-        hipStream_t cs =
-            (j == 0 || nstreams == 1) ? st[0] : st[others0 + (j - 1) % (nstreams - others0)];
+        hipStream_t cs = st[0];
+        if (j > 0 && nstreams > 1) {
+            // the side stream with the least work so far (work of a class:
+            // its vertices times its largest n, about its n^2 entries), so
+            // that small classes pile up behind each other rather than behind
+            // a large one
+            int best = others0;
+            for (int k = others0 + 1; k < nstreams; ++k)
+                if (load[k] < load[best]) best = k;
+            load[best] += (double)plan.class_vertices[c] * (double)kClassMaxN[c];
+            cs = st[best];
+        }
         e = trees(first, count, plan.class_vertices[c], cs);
         if (e != hipSuccess) return e;
         if (stagger && j == 0 && (e = fork()) != hipSuccess) return e;

@@ -823,8 +823,8 @@ int appd_backward_points_batched(const float* X, int d, const float* W, const fl
         return fail(APPD_EINVAL);
     Tables t = carve(ws, plan->num_graphs, plan->total_n);
     hipStream_t s = (hipStream_t)stream;
+    // dX needs no clearing: the chain's first launch writes every entry
     hipError_t e = appd::run_zero(t.gedge, 4 * (size_t)plan->total_n, s);
-    if (e == hipSuccess) e = appd::run_zero(dX, 4 * (size_t)plan->total_n * d, s);
     if (e == hipSuccess) e = appd::run_scale_offsets(t.noff, plan->num_graphs, d, t.xoff, s);
     if (e == hipSuccess)
         e = appd::run_edge_grad(G, idx, t.offsets, t.noff, t.ns, parent, t.gchunk_start,
@@ -878,8 +878,8 @@ int appd_backward_points(const float* X, int n, int d, const float* W, const flo
     if (rc != APPD_OK) return rc == APPD_EHIP ? hip_status(hipErrorUnknown) : fail(rc);
     const int chunks = (n + appd::kGradRows - 1) / appd::kGradRows;
     const int vblocks = (n + appd::kChainThreads - 1) / appd::kChainThreads;
+    // dX needs no clearing: the chain's first launch writes every entry
     hipError_t e = appd::run_zero(t.gedge, 4 * (size_t)n, s);
-    if (e == hipSuccess) e = appd::run_zero(dX, 4 * (size_t)n * d, s);
     if (e == hipSuccess) e = appd::run_scale_offsets(t.noff, 1, d, t.xoff, s);
     if (e == hipSuccess)
         e = appd::run_edge_grad(G, idx, t.offsets, t.noff, t.ns, parent, t.gchunk_start, 1,

@@ -233,10 +233,38 @@ __global__ __launch_bounds__(256) void edge_grad_kernel(
     }
 }
 
-// dX[c] += g_c (x_c - x_p) / w_cp, dX[p] -= the same, for every non-root c.
-__global__ __launch_bounds__(256) void chain_points_kernel(
+// The chain rule through w = ||x_c - x_p|| for every edge (c, parent c), in
+// two launches.  The first writes every vertex's own term, dX[c] = f_c (x_c -
+// x_p) with f_c = g_c / w_cp (0 at the root), with plain stores (each vertex
+// is the child of one edge, so dX needs no clearing), and leaves f_c in
+// gedge[c].  The second adds -f_c (x_c - x_p) to the parent's row, the only
+// part several edges share (atomics).
+__global__ __launch_bounds__(256) void chain_child_kernel(
     const float* __restrict__ X, const int64_t* __restrict__ xoff,
     const float* __restrict__ W, const int64_t* __restrict__ offsets,
+    const int64_t* __restrict__ noff, const int32_t* __restrict__ ns,
+    const int32_t* __restrict__ parent, float* __restrict__ gedge,
+    const int32_t* __restrict__ vstart, int num_graphs, int d, float* __restrict__ dX) {
+    const int g = find_item(vstart, num_graphs, blockIdx.x);
+    const int n = ns[g];
+    const int c = (blockIdx.x - vstart[g]) * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const int p = parent[noff[g] + c];
+    float f = 0.0f;
+    if (p >= 0) {
+        const float gv = gedge[noff[g] + c];
+        const float w = W[offsets[g] + (size_t)c * n + p];
+        if (gv != 0.0f && w > 0.0f) f = gv / w;
+    }
+    gedge[noff[g] + c] = f;
+    const float* Xg = X + xoff[g];
+    float* dXg = dX + xoff[g];
+    for (int t = 0; t < d; ++t)
+        dXg[(size_t)c * d + t] = f != 0.0f ? f * (Xg[(size_t)c * d + t] - Xg[(size_t)p * d + t]) : 0.0f;
+}
+
+__global__ __launch_bounds__(256) void chain_points_kernel(
+    const float* __restrict__ X, const int64_t* __restrict__ xoff,
     const int64_t* __restrict__ noff, const int32_t* __restrict__ ns,
     const int32_t* __restrict__ parent, const float* __restrict__ gedge,
     const int32_t* __restrict__ vstart, int num_graphs, int d, float* __restrict__ dX) {
@@ -245,18 +273,12 @@ __global__ __launch_bounds__(256) void chain_points_kernel(
     const int c = (blockIdx.x - vstart[g]) * blockDim.x + threadIdx.x;
     if (c >= n) return;
     const int p = parent[noff[g] + c];
-    if (p < 0) return;
-    const float gv = gedge[noff[g] + c];
-    const float w = W[offsets[g] + (size_t)c * n + p];
-    if (gv == 0.0f || !(w > 0.0f)) return;
-    const float f = gv / w;
+    const float f = gedge[noff[g] + c];
+    if (p < 0 || f == 0.0f) return;
     const float* Xg = X + xoff[g];
     float* dXg = dX + xoff[g];
-    for (int t = 0; t < d; ++t) {
-        const float df = Xg[(size_t)c * d + t] - Xg[(size_t)p * d + t];
-        atomicAdd(&dXg[(size_t)c * d + t], f * df);
-        atomicAdd(&dXg[(size_t)p * d + t], -f * df);
-    }
+    for (int t = 0; t < d; ++t)
+        atomicAdd(&dXg[(size_t)p * d + t], -f * (Xg[(size_t)c * d + t] - Xg[(size_t)p * d + t]));
 }
 
 hipError_t run_pairwise(const float* X, const int64_t* xoff, const int64_t* offsets,
@@ -295,12 +317,17 @@ hipError_t run_edge_grad(const float* G, const int32_t* idx, const int64_t* offs
 
 hipError_t run_chain(const float* X, const int64_t* xoff, const float* W, const int64_t* offsets,
                      const int64_t* noff, const int32_t* ns, const int32_t* parent,
-                     const float* gedge, const int32_t* vstart, int num_graphs, int total_vblocks,
+                     float* gedge, const int32_t* vstart, int num_graphs, int total_vblocks,
                      int d, float* dX, hipStream_t s) {
     if (total_vblocks == 0) return hipSuccess;
-    APPD_LAUNCH("chain_points_kernel", s,
-        chain_points_kernel<<<total_vblocks, 256, 0, s>>>(X, xoff, W, offsets, noff, ns, parent,
+    APPD_LAUNCH("chain_child_kernel", s,
+        chain_child_kernel<<<total_vblocks, 256, 0, s>>>(X, xoff, W, offsets, noff, ns, parent,
             gedge, vstart, num_graphs, d, dX));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    APPD_LAUNCH("chain_points_kernel", s,
+        chain_points_kernel<<<total_vblocks, 256, 0, s>>>(X, xoff, noff, ns, parent, gedge,
+            vstart, num_graphs, d, dX));
     return hipGetLastError();
 }
 

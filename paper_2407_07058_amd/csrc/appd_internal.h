@@ -156,7 +156,7 @@ hipError_t run_edge_grad(const float* G, const int32_t* idx, const int64_t* offs
                          int rows_per_wg, int max_n, float* gedge, hipStream_t s);
 hipError_t run_chain(const float* X, const int64_t* xoff, const float* W, const int64_t* offsets,
                      const int64_t* noff, const int32_t* ns, const int32_t* parent,
-                     const float* gedge, const int32_t* vstart, int num_graphs, int total_vblocks,
+                     float* gedge, const int32_t* vstart, int num_graphs, int total_vblocks,
                      int d, float* dX, hipStream_t s);
 hipError_t run_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t run_scale_offsets(const int64_t* noff, int num_graphs, int d, int64_t* xoff,

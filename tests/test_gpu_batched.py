@@ -532,3 +532,45 @@ def test_differentiable_batch_full_config():
     assert all(r[0] for r in res), "forward mismatch in graphs %s" % [g for g, r in enumerate(res) if not r[0]][:5]
     bad = [(g, r[2]) for g, r in enumerate(res) if not r[1]]
     assert not bad, "gradient outside tolerance: %s" % bad[:5]
+
+
+def clustered_graph(k, per, seed, dim=3):
+    """k far-apart clusters of `per` points: every vertex's 16 nearest
+    neighbours lie in its own cluster once per > 16."""
+    rng = np.random.default_rng(seed)
+    centres = rng.random((k, dim)) * 1000.0
+    X = np.repeat(centres, per, axis=0) + 0.5 * rng.standard_normal((k * per, dim))
+    X = X[rng.permutation(len(X))]
+    return workloads.euclid_w(X)
+
+
+@pytest.mark.parametrize("mode", [appd.MINIMAX, appd.WIDEST])
+def test_batched_boruvka_refresh_and_fallback(mode):
+    """Graphs of many far-apart clusters: their candidate lists stay inside the
+    clusters, so the per-graph Boruvka workgroup must refresh the lists of a
+    stuck component's used-up vertices (rank top-K with the component masked,
+    or the insertion list in 1024-thread workgroups), and with more stuck
+    components than refreshes allowed it finishes with Prim's algorithm.
+    Every graph equals the oracle; the stats show both paths taken."""
+    say("case batched refresh and fallback mode=%d" % mode)
+    Ws = [clustered_graph(3, 40, 1), clustered_graph(5, 60, 2), clustered_graph(20, 20, 3),
+          clustered_graph(12, 70, 4), clustered_graph(30, 30, 5), clustered_graph(4, 300, 6),
+          clustered_graph(30, 50, 7), workloads.random_symmetric(700, seed=8)]
+    if mode == appd.WIDEST:  # the maximum spanning tree of c - W keeps the clusters
+        Ws = [np.float32(W.max() + 1.0) - W for W in Ws]
+        for W in Ws:
+            np.fill_diagonal(W, 0.0)
+    flat, offsets, ns = workloads.pack(Ws)
+    b = appd.Batch(ns, DEV)
+    b.set_schedule(trees="boruvka", streams=1)
+    M, idx = b.forward(torch.from_numpy(flat).to(DEV), mode=mode)
+    torch.cuda.synchronize()
+    st = b.tree_stats()
+    Ms = unpack(M.cpu().numpy(), ns, offsets)
+    Is = unpack(idx.cpu().numpy(), ns, offsets)
+    ref = oracle.appd_widest if mode == appd.WIDEST else oracle.appd
+    for g, W in enumerate(Ws):
+        Mo, io = ref(W)
+        assert np.array_equal(Ms[g].view(np.uint32), Mo.view(np.uint32)), (g, int(ns[g]))
+        assert np.array_equal(Is[g], io), (g, int(ns[g]))
+    assert st["multi_pass"] >= 2 and st["fallback"] >= 1, st

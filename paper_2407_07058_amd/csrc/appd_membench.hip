@@ -1,4 +1,4 @@
-// Measurement aids: the reference points the kernels are judged against, taken
+// Measurement aids: the reference points the kernels are compared with, taken
 // on the same GPU.
 //
 //  - a streaming copy and a streaming store (16-byte vectors, grid-stride, a

@@ -81,14 +81,23 @@ __device__ __forceinline__ void upper_tile(int b, int nt, int* bi, int* bj) {
 // One workgroup per upper-triangle tile pair (ti <= tj): the 64 x 64 block of
 // W at rows ti, columns tj is computed once and written there and, through an
 // LDS transpose, at rows tj, columns ti (W is bit-symmetric: the differences of
-// the mirrored pair are negations, their squares equal).
+// the mirrored pair are negations, their squares equal).  LDS (sized for d,
+// pairwise_lds_bytes): the row block's points, 64 x (d + 1), later the 64 x 65
+// transpose tile in the same place; then the column block's points
+// transposed, d x 65.
+constexpr int kPairTileWords = kTile * (kTile + 1);
+static_assert(kMaxD <= kTile, "a 64 x (d + 1) point block fits the transpose tile");
+
+inline size_t pairwise_lds_bytes(int d) { return 4 * ((size_t)kPairTileWords + (size_t)d * (kTile + 1)); }
+
 __global__ __launch_bounds__(kPairThreads) void pairwise_kernel(
     const float* __restrict__ X, const int64_t* __restrict__ xoff,
     const int64_t* __restrict__ offsets, const int32_t* __restrict__ ns,
     const int32_t* __restrict__ tile_start, int num_graphs, int d, float* __restrict__ W) {
-    __shared__ float xi[kTile][kMaxD + 1];
-    __shared__ float xjT[kMaxD][kTile + 1];
-    static_assert(kMaxD >= kTile, "the transpose reuses xi as a 64 x 65 tile");
+    extern __shared__ float s_pair[];
+    float* xs = s_pair;                    // xi[r][t] = xs[r * (d + 1) + t]; tile[r][c] = xs[r * 65 + c]
+    float* xt = s_pair + kPairTileWords;   // xjT[t][c] = xt[t * 65 + c]
+    const int dp = d + 1;
     const int g = find_item(tile_start, num_graphs, blockIdx.x);
     const int n = ns[g];
     const int nt = (n + kTile - 1) / kTile;
@@ -100,8 +109,8 @@ __global__ __launch_bounds__(kPairThreads) void pairwise_kernel(
     const int i0 = ti * kTile, j0 = tj * kTile;
     for (int e = threadIdx.x; e < kTile * d; e += kPairThreads) {
         const int r = e / d, t = e % d;
-        xi[r][t] = (i0 + r < n) ? Xg[(size_t)(i0 + r) * d + t] : 0.0f;
-        xjT[t][r] = (j0 + r < n) ? Xg[(size_t)(j0 + r) * d + t] : 0.0f;
+        xs[r * dp + t] = (i0 + r < n) ? Xg[(size_t)(i0 + r) * d + t] : 0.0f;
+        xt[t * (kTile + 1) + r] = (j0 + r < n) ? Xg[(size_t)(j0 + r) * d + t] : 0.0f;
     }
     __syncthreads();
     const int c = threadIdx.x & (kTile - 1);
@@ -116,22 +125,22 @@ __global__ __launch_bounds__(kPairThreads) void pairwise_kernel(
         if (i >= n || j >= n) continue;
         float acc = 0.0f;
         for (int t = 0; t < d; ++t) {
-            const float df = __fsub_rn(xi[r][t], xjT[t][c]);
+            const float df = __fsub_rn(xs[r * dp + t], xt[t * (kTile + 1) + c]);
             acc = __fadd_rn(acc, __fmul_rn(df, df));
         }
         vals[k] = (i == j) ? 0.0f : sqrt_rn_exact(acc);
         Wg[(size_t)i * n + j] = vals[k];
     }
     if (ti == tj) return;  // workgroup-uniform: a diagonal block is its own mirror
-    __syncthreads();       // xi is read no more: it becomes the transpose tile
+    __syncthreads();       // the point block is read no more: it becomes the transpose tile
 #pragma unroll
-    for (int k = 0; k < kTile / RS; ++k) xi[threadIdx.x / kTile + RS * k][c] = vals[k];
+    for (int k = 0; k < kTile / RS; ++k) xs[(threadIdx.x / kTile + RS * k) * (kTile + 1) + c] = vals[k];
     __syncthreads();
     const int ic = i0 + c;  // column of the mirrored block
 #pragma unroll
     for (int k = 0; k < kTile / RS; ++k) {
         const int jr = threadIdx.x / kTile + RS * k;  // row of the mirrored block
-        if (j0 + jr < n && ic < n) Wg[(size_t)(j0 + jr) * n + ic] = xi[c][jr];
+        if (j0 + jr < n && ic < n) Wg[(size_t)(j0 + jr) * n + ic] = xs[c * (kTile + 1) + jr];
     }
 }
 
@@ -287,8 +296,8 @@ hipError_t run_pairwise(const float* X, const int64_t* xoff, const int64_t* offs
     if (d < 1 || d > kMaxD) return hipErrorInvalidValue;
     if (total_tiles == 0) return hipSuccess;
     APPD_LAUNCH("pairwise_kernel", s,
-        pairwise_kernel<<<total_tiles, kPairThreads, 0, s>>>(X, xoff, offsets, ns, tile_start,
-            num_graphs, d, W));
+        pairwise_kernel<<<total_tiles, kPairThreads, pairwise_lds_bytes(d), s>>>(
+            X, xoff, offsets, ns, tile_start, num_graphs, d, W));
     return hipGetLastError();
 }
 

@@ -194,11 +194,11 @@ __global__ __launch_bounds__(256) void edge_grad_kernel(
     const int r0 = chunk * rows_per_wg, r1 = min(n, r0 + rows_per_wg);
     for (int r = r0 + wave; r < r1; r += blockDim.x / kWave) {
         // Most of a row's pairs share one bottleneck, nearly always the edge
-        // of the row's own vertex or of its parent (slots r and parent[r]):
-        // those two are summed in registers, so that the bins' atomics see
-        // few lanes on one address.
-        const int sa = r, sb = par[r];
-        float acc_a = 0.0f, acc_b = 0.0f;
+        // of the row's own vertex, of its parent or of its grandparent (slots
+        // r, parent[r], parent[parent[r]]): those three are summed in
+        // registers, so that the bins' atomics see few lanes on one address.
+        const int sa = r, sb = par[r], sc = sb >= 0 ? par[sb] : -1;
+        float acc_a = 0.0f, acc_b = 0.0f, acc_c = 0.0f;
         const __amdgpu_buffer_rsrc_t ri = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<int32_t*>(Ig + (size_t)r * n), (short)0, n * 4, kBufferRsrcWord3);
         const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(
@@ -220,6 +220,7 @@ __global__ __launch_bounds__(256) void edge_grad_kernel(
                     const int sl = edge_slot(f[e], n, rcp_n, par);
                     if (sl == sa) acc_a += gv[e];
                     else if (sl == sb) acc_b += gv[e];
+                    else if (sl == sc) acc_c += gv[e];
                     else atomicAdd(&hist[sl], gv[e]);
                 }
             }
@@ -228,10 +229,12 @@ __global__ __launch_bounds__(256) void edge_grad_kernel(
         for (int m = kWave / 2; m >= 1; m >>= 1) {
             acc_a += __shfl_xor(acc_a, m);
             acc_b += __shfl_xor(acc_b, m);
+            acc_c += __shfl_xor(acc_c, m);
         }
         if (lane == 0) {
             atomicAdd(&hist[sa], acc_a);
             if (sb >= 0) atomicAdd(&hist[sb], acc_b);
+            if (sc >= 0) atomicAdd(&hist[sc], acc_c);
         }
     }
     __syncthreads();
